@@ -1,0 +1,206 @@
+/*
+ * scivr.h -- C ABI of the MI355X (gfx950) TA-SC-IVR power-spectrum library.
+ *
+ * The library computes the time-averaged semiclassical initial value
+ * representation spectral density with the separable prefactor
+ * approximation (Tamascelli, Dambrosio, Conte, Ceotto, "Graphics Processing
+ * Units Accelerated Semiclassical Initial Value Representation Molecular
+ * Dynamics", Eq. (10)) by the Monte Carlo estimator of Eq. (11):
+ *
+ *   I(E_k) = dt^2 / (2 pi T n_good) * sum_j good_j w_j
+ *            | sum_{c=0}^{n_steps} <chi|p_j(c dt), q_j(c dt)> e^{i (S_j + E_k c dt + phi_j)} |^2
+ *
+ * with T = n_steps dt, w_j = 1 / ((2 pi)^F rho(p0_j, q0_j)) for initial
+ * points drawn from a density rho (Husimi sampling of the reference coherent
+ * state chi gives w_j = 1/|<p0_j,q0_j|chi>|^2), the energy grid
+ * E_k = e_min + k (e_max - e_min)/(K - 1) of the section "Monte-Carlo SC-IVR
+ * algorithm", and good_j = 0 for a trajectory whose |det(M)^2 - 1| exceeded
+ * det_tol at a checked step (the accuracy monitor after Eq. (5)).
+ *
+ * Units: atomic units, hbar = 1, mass-weighted coordinates.  The potential is
+ *   V(q) = sum_i [k_i q_i^2/2 + D_i (1 - exp(-a_i q_i))^2] + sum_{i<j} lambda_ij q_i^2 q_j^2.
+ *
+ * Conventions common to every call:
+ *  - Return values are scivr_status codes (<= 0).  No C++ exception, abort or
+ *    exit crosses the ABI.  After an error, scivr_last_error(ctx) describes it.
+ *  - A device error (a failed HIP call) is sticky: every later call on that
+ *    context returns SCIVR_EDEVICE.
+ *  - `stream` is a hipStream_t passed as void*; NULL means the legacy default
+ *    stream.  Calls taking a stream are asynchronous on it unless stated.
+ *  - One context per host thread at a time; a context is not thread-safe.
+ *  - Phase-space arrays are structure-of-arrays [F][n] (all trajectories'
+ *    values of degree of freedom 0, then of degree of freedom 1, ...), the
+ *    coalesced layout described in the section "GP-GPU Implementation".
+ */
+#ifndef SCIVR_H
+#define SCIVR_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SCIVR_ABI_VERSION 1
+/* Largest number of degrees of freedom of the FP64 trajectory kernel. */
+#define SCIVR_F_MAX 16
+
+typedef int32_t scivr_status;
+#define SCIVR_OK 0
+#define SCIVR_EINVAL (-1)       /* invalid argument */
+#define SCIVR_ENOMEM (-2)       /* device or host allocation failed */
+#define SCIVR_EDEVICE (-3)      /* a HIP call failed (sticky) */
+#define SCIVR_ESTATE (-4)       /* call out of order (e.g. propagate before initial conditions) */
+#define SCIVR_ENOGOOD (-5)      /* no good trajectory accumulated yet; spectrum zero-filled */
+#define SCIVR_EUNSUPPORTED (-6) /* valid request this build does not implement */
+
+#define SCIVR_PRECISION_FP64 0  /* every step in FP64 */
+#define SCIVR_PRECISION_MIXED 1 /* FP32 trajectory, FP64 monodromy/prefactor, split-BF16 Fourier GEMM */
+
+#define SCIVR_MEM_HOST 0
+#define SCIVR_MEM_DEVICE 1
+
+/*
+ * Problem statement.  All arrays are read during scivr_create and copied;
+ * the caller keeps ownership.  `lambda` is F x F row-major and symmetric;
+ * only the entries i < j are read (the diagonal is ignored).
+ */
+typedef struct scivr_problem {
+    int32_t F;               /* degrees of freedom, 1 <= F <= SCIVR_F_MAX */
+    const double *k_harm;    /* [F] harmonic coefficients k_i */
+    const double *morse_D;   /* [F] Morse depths D_i */
+    const double *morse_a;   /* [F] Morse range parameters a_i */
+    const double *lambda;    /* [F*F] quartic couplings lambda_ij */
+    const double *gamma;     /* [F] coherent-state widths gamma_i > 0 (Eq. (3)) */
+    const double *p_eq;      /* [F] reference state chi = |p_eq, q_eq> */
+    const double *q_eq;      /* [F] */
+    double dt;               /* time step (> 0) */
+    int32_t n_steps;         /* steps per trajectory (>= 1); T = n_steps dt */
+    double e_min, e_max;     /* energy window, e_max > e_min */
+    int32_t n_energies;      /* K >= 2 grid points, both ends included */
+    double det_tol;          /* stability threshold on |det(M)^2 - 1| (paper: 1e-6) */
+    int32_t check_every;     /* check det(M) every this many steps (and at the last step); 1 = every step */
+    int32_t precision;       /* SCIVR_PRECISION_* */
+    int64_t max_traj;        /* batch capacity: largest n_traj of one batch (>= 1) */
+} scivr_problem;
+
+typedef struct scivr_ctx scivr_ctx;
+
+/* Version of this ABI (SCIVR_ABI_VERSION of the built library). */
+int32_t scivr_abi_version(void);
+
+/*
+ * Validate the problem, select `device`, copy the parameters and allocate
+ * every device buffer of a batch of max_traj trajectories (initial
+ * conditions, state, the [n_steps+1][max_traj] complex amplitude matrix, the
+ * time x energy phase table, spectrum accumulators).
+ * Errors: SCIVR_EINVAL (F out of range, n_steps < 1, n_energies < 2,
+ * e_max <= e_min, gamma_i <= 0, dt <= 0, check_every < 1, max_traj < 1, a
+ * non-finite parameter, NULL pointer), SCIVR_EUNSUPPORTED (precision not
+ * built for this F), SCIVR_ENOMEM, SCIVR_EDEVICE.  On error *out is NULL and
+ * nothing is leaked.
+ */
+scivr_status scivr_create(const scivr_problem *p, int32_t device, scivr_ctx **out);
+
+/* Free every resource of the context (synchronises its device first). NULL is ignored. */
+void scivr_destroy(scivr_ctx *ctx);
+
+/* Message of the last error on this context ("" if none).  Valid until the next call. */
+const char *scivr_last_error(const scivr_ctx *ctx);
+
+/*
+ * Husimi sampling of chi (section "Monte-Carlo SC-IVR algorithm"): for
+ * trajectory j of the batch, global index g = first_index + j, the 2F
+ * standard normals are Box-Muller pairs of the uniforms of Philox4x64-10
+ * blocks with key (seed, 0) and counter (g, b, 0, 0), b = 0, 1, ...; normal
+ * 2i is xi_i and normal 2i+1 is eta_i, and
+ *   q0_i = q_eq,i + xi_i / sqrt(gamma_i),  p0_i = p_eq,i + eta_i sqrt(gamma_i),
+ *   ln rho = -F ln(2 pi) - sum_i (xi_i^2 + eta_i^2)/2.
+ * Sets the batch size to n_traj (1 <= n_traj <= max_traj) and resets the
+ * propagation state.  Disjoint first_index ranges give independent batches.
+ */
+scivr_status scivr_sample_husimi(scivr_ctx *ctx, uint64_t seed, uint64_t first_index, int64_t n_traj,
+                                 void *stream);
+
+/*
+ * Use caller-given initial conditions: p0, q0 are [F][n_traj], log_density
+ * [n_traj] is ln rho(p0, q0) of the density they were drawn from (it sets
+ * the weight w_j = exp(-ln rho_j - F ln 2 pi)).  mem_kind says whether the
+ * pointers are host or device memory; device pointers are read on `stream`
+ * and must stay valid until that work completes.  Sets the batch size and
+ * resets the propagation state.
+ */
+scivr_status scivr_set_initial(scivr_ctx *ctx, int64_t n_traj, const double *p0, const double *q0,
+                               const double *log_density, int32_t mem_kind, void *stream);
+
+/*
+ * Integrate the batch over steps [step_begin, step_end) (0 <= step_begin <
+ * step_end <= n_steps): the fourth-order symplectic triple jump with three
+ * Hessian evaluations per step, the action, the 2F x 2F monodromy matrix, the
+ * continuous phase of the Herman-Kluk prefactor (Eq. (5)), the stability
+ * monitor, and the amplitude of every time sample.  Calls must continue
+ * where the last one stopped (step_begin == steps done), else SCIVR_ESTATE;
+ * SCIVR_ESTATE also without initial conditions.
+ */
+scivr_status scivr_propagate(scivr_ctx *ctx, int32_t step_begin, int32_t step_end, void *stream);
+
+/*
+ * After all n_steps are done: the Fourier sums A_jk = sum_c amp_jc e^{i E_k c dt}
+ * of the batch, and ADD sum_j good_j w_j |A_jk|^2 and the batch's n_good
+ * and n_traj into the context's running totals (so several batches form one
+ * estimate).  Also stores each trajectory's contribution w_j sum_k |A_jk|^2.
+ * SCIVR_ESTATE if the batch is not fully propagated or was already added.
+ */
+scivr_status scivr_accumulate_spectrum(scivr_ctx *ctx, void *stream);
+
+/*
+ * Synchronise and write I_k = dt^2/(2 pi T n_good) * total_k to I_host[K]
+ * (caller-owned), and the running n_good and n_total.  If n_good is 0 the
+ * spectrum is zero-filled and SCIVR_ENOGOOD is returned.  Any output pointer
+ * may be NULL.
+ */
+scivr_status scivr_read_spectrum(scivr_ctx *ctx, double *I_host, int64_t *n_good, int64_t *n_total);
+
+/* Zero the running spectrum totals and counts (asynchronous on `stream`). */
+scivr_status scivr_reset_spectrum(scivr_ctx *ctx, void *stream);
+
+/* ---- inspection (parity checks and diagnostics); all synchronise and write host memory ---- */
+
+/* Current batch size (0 before initial conditions) and steps done. */
+scivr_status scivr_batch_info(const scivr_ctx *ctx, int64_t *n_traj, int32_t *steps_done);
+
+/* Initial conditions of the batch: p0, q0 [F][n], log_density [n]. Any may be NULL. */
+scivr_status scivr_read_initial(scivr_ctx *ctx, double *p0, double *q0, double *log_density);
+
+/*
+ * State after the last propagate call: p, q [F][n]; S, phi, detM (det M at
+ * the last checked step), maxdev (max |det(M)^2 - 1| over checked steps) [n];
+ * M [n][2F][2F] row-major with rows and columns ordered (p, q), i.e.
+ * M[j][r][c] = d(p,q)_r(t) / d(p0,q0)_c; good [n] (1 or 0).  Any may be NULL.
+ */
+scivr_status scivr_read_state(scivr_ctx *ctx, double *p, double *q, double *S, double *phi, double *M,
+                              uint8_t *good, double *detM, double *maxdev);
+
+/* Amplitudes of trajectories [j0, j0 + count) at every time sample: amp[count][n_steps+1][2] (re, im). */
+scivr_status scivr_read_amplitudes(scivr_ctx *ctx, int64_t j0, int64_t count, double *amp);
+
+/* Per-trajectory contributions w_j sum_k |A_jk|^2 (0 for bad) of the last accumulated batch: c[n]. */
+scivr_status scivr_read_contributions(scivr_ctx *ctx, double *c);
+
+/*
+ * Kernel timing.  While enabled, every kernel launch of the context is
+ * bracketed by HIP events on its stream.  scivr_kernel_times synchronises
+ * and returns, per kernel kind, the number of launches and their summed
+ * duration in milliseconds since the last reset (enable resets).  Kinds:
+ * 0 = sample, 1 = trajectory, 2 = Fourier GEMM, 3 = spectrum reduction.
+ */
+#define SCIVR_KERNEL_KINDS 4
+scivr_status scivr_timing_enable(scivr_ctx *ctx, int32_t on);
+scivr_status scivr_kernel_times(scivr_ctx *ctx, int64_t *launches /*[SCIVR_KERNEL_KINDS]*/,
+                                double *ms /*[SCIVR_KERNEL_KINDS]*/);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SCIVR_H */

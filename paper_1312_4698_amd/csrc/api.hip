@@ -1,0 +1,559 @@
+// C ABI of libscivr (declared in include/scivr.h): argument validation,
+// device buffers of one batch, kernel launches and host-side bookkeeping.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <cmath>
+
+#include <new>
+#include <string>
+#include <vector>
+
+#include "scivr.h"
+#include "scivr_internal.h"
+
+using namespace scivr;
+
+struct EventPair {
+    hipEvent_t a, b;
+    int kind;
+};
+
+struct scivr_ctx {
+    int device = 0;
+    int F = 0;
+    int32_t n_steps = 0, n_energies = 0, check_every = 1, precision = 0;
+    double dt = 0, e_min = 0, e_max = 0, det_tol = 0;
+    int64_t max_traj = 0, npad = 0;
+    int32_t nt = 0, nt_pad = 0, nt_alloc = 0, kpad = 0, row_tiles = 0, col_tiles = 0;
+
+    ProblemDev host_prob{};
+    ProblemDev *d_prob = nullptr;
+    double *d_p0 = nullptr, *d_q0 = nullptr, *d_logrho = nullptr;
+    double *d_p = nullptr, *d_q = nullptr, *d_scal = nullptr, *d_M = nullptr;
+    double2 *d_amp = nullptr, *d_phase = nullptr;
+    double *d_weight = nullptr, *d_part_spec = nullptr, *d_part_contrib = nullptr, *d_contrib = nullptr;
+    double *d_total = nullptr;
+    unsigned long long *d_ngood = nullptr;
+
+    int64_t n_traj = 0;      // current batch size
+    int32_t steps_done = 0;
+    bool have_initial = false, accumulated = false;
+    int64_t n_total = 0;     // trajectories accumulated so far
+
+    bool device_error = false;
+    std::string err;
+
+    bool timing = false;
+    std::vector<EventPair> events;
+};
+
+namespace {
+
+scivr_status fail(scivr_ctx *c, scivr_status st, const char *fmt, ...) __attribute__((format(printf, 3, 4)));
+scivr_status fail(scivr_ctx *c, scivr_status st, const char *fmt, ...)
+{
+    if (c) {
+        char buf[512];
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(buf, sizeof buf, fmt, ap);
+        va_end(ap);
+        c->err = buf;
+        if (st == SCIVR_EDEVICE) c->device_error = true;
+    }
+    return st;
+}
+
+#define HIPCALL(ctx, expr)                                                                                  \
+    do {                                                                                                    \
+        hipError_t e_ = (expr);                                                                             \
+        if (e_ != hipSuccess)                                                                               \
+            return fail((ctx), SCIVR_EDEVICE, "%s failed: %s (%s:%d)", #expr, hipGetErrorString(e_), __FILE__, \
+                        __LINE__);                                                                          \
+    } while (0)
+
+#define CHECK_CTX(ctx)                                                                        \
+    do {                                                                                      \
+        if (!(ctx)) return SCIVR_EINVAL;                                                      \
+        if ((ctx)->device_error) return SCIVR_EDEVICE;                                        \
+        hipError_t e_ = hipSetDevice((ctx)->device);                                          \
+        if (e_ != hipSuccess) return fail((ctx), SCIVR_EDEVICE, "hipSetDevice: %s", hipGetErrorString(e_)); \
+    } while (0)
+
+int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
+
+bool finite_all(const double *a, int n)
+{
+    for (int i = 0; i < n; ++i)
+        if (!std::isfinite(a[i])) return false;
+    return true;
+}
+
+template <typename T>
+hipError_t dalloc(T **p, size_t count)
+{
+    return hipMalloc((void **)p, count * sizeof(T) + 256);
+}
+
+void free_all(scivr_ctx *c)
+{
+    void *ptrs[] = {c->d_prob, c->d_p0, c->d_q0, c->d_logrho, c->d_p, c->d_q, c->d_scal, c->d_M, c->d_amp,
+                    c->d_phase, c->d_weight, c->d_part_spec, c->d_part_contrib, c->d_contrib, c->d_total, c->d_ngood};
+    for (void *p : ptrs)
+        if (p) (void)hipFree(p);
+    for (auto &e : c->events) {
+        (void)hipEventDestroy(e.a);
+        (void)hipEventDestroy(e.b);
+    }
+    c->events.clear();
+}
+
+// Bracket a launch with timing events when enabled.
+struct Timed {
+    scivr_ctx *c;
+    hipStream_t s;
+    int kind;
+    hipEvent_t a = nullptr, b = nullptr;
+    Timed(scivr_ctx *c_, hipStream_t s_, int k) : c(c_), s(s_), kind(k)
+    {
+        if (c->timing) {
+            if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
+                a = b = nullptr;
+                return;
+            }
+            (void)hipEventRecord(a, s);
+        }
+    }
+    void done()
+    {
+        if (a && b) {
+            (void)hipEventRecord(b, s);
+            c->events.push_back({a, b, kind});
+            a = b = nullptr;
+        }
+    }
+    ~Timed()
+    {
+        if (a) (void)hipEventDestroy(a);
+        if (b) (void)hipEventDestroy(b);
+    }
+};
+
+}  // namespace
+
+extern "C" {
+
+int32_t scivr_abi_version(void) { return SCIVR_ABI_VERSION; }
+
+const char *scivr_last_error(const scivr_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+scivr_status scivr_create(const scivr_problem *p, int32_t device, scivr_ctx **out)
+{
+    if (!out) return SCIVR_EINVAL;
+    *out = nullptr;
+    if (!p) return SCIVR_EINVAL;
+    const int F = p->F;
+    if (F < 1 || F > SCIVR_F_MAX) return SCIVR_EINVAL;
+    if (!p->k_harm || !p->morse_D || !p->morse_a || !p->lambda || !p->gamma || !p->p_eq || !p->q_eq)
+        return SCIVR_EINVAL;
+    if (p->n_steps < 1 || p->n_energies < 2 || !(p->e_max > p->e_min) || !(p->dt > 0) || p->check_every < 1 ||
+        p->max_traj < 1 || !(p->det_tol >= 0))
+        return SCIVR_EINVAL;
+    if (!std::isfinite(p->dt) || !std::isfinite(p->e_min) || !std::isfinite(p->e_max) || !std::isfinite(p->det_tol))
+        return SCIVR_EINVAL;
+    if (!finite_all(p->k_harm, F) || !finite_all(p->morse_D, F) || !finite_all(p->morse_a, F) ||
+        !finite_all(p->lambda, F * F) || !finite_all(p->gamma, F) || !finite_all(p->p_eq, F) ||
+        !finite_all(p->q_eq, F))
+        return SCIVR_EINVAL;
+    for (int i = 0; i < F; ++i)
+        if (!(p->gamma[i] > 0)) return SCIVR_EINVAL;
+    if (p->precision != SCIVR_PRECISION_FP64 && p->precision != SCIVR_PRECISION_MIXED) return SCIVR_EINVAL;
+    if (p->precision != SCIVR_PRECISION_FP64) return SCIVR_EUNSUPPORTED;
+    if ((int64_t)p->n_steps + 1 > (int64_t)INT32_MAX - 64 || p->n_energies > (1 << 24) || p->max_traj > (1ll << 31))
+        return SCIVR_EINVAL;
+
+    scivr_ctx *c = new (std::nothrow) scivr_ctx();
+    if (!c) return SCIVR_ENOMEM;
+    c->device = device;
+    c->F = F;
+    c->n_steps = p->n_steps;
+    c->n_energies = p->n_energies;
+    c->check_every = p->check_every;
+    c->precision = p->precision;
+    c->dt = p->dt;
+    c->e_min = p->e_min;
+    c->e_max = p->e_max;
+    c->det_tol = p->det_tol;
+    c->max_traj = p->max_traj;
+    c->npad = round_up(p->max_traj, GEMM_BM);
+    c->nt = p->n_steps + 1;
+    c->nt_pad = (int32_t)round_up(c->nt, GEMM_BK);
+    c->nt_alloc = c->nt_pad + GEMM_BK;
+    c->kpad = (int32_t)round_up(p->n_energies, GEMM_BN);
+    c->row_tiles = (int32_t)(c->npad / GEMM_BM);
+    c->col_tiles = c->kpad / GEMM_BN;
+
+    // trajectory-independent constants
+    ProblemDev &h = c->host_prob;
+    memset(&h, 0, sizeof h);
+    double sg = 0.0;
+    for (int i = 0; i < F; ++i) {
+        h.k[i] = p->k_harm[i];
+        h.D[i] = p->morse_D[i];
+        h.a[i] = p->morse_a[i];
+        h.gamma[i] = p->gamma[i];
+        h.sqrt_gamma[i] = sqrt(p->gamma[i]);
+        h.inv_sqrt_gamma[i] = 1.0 / h.sqrt_gamma[i];
+        h.inv4gamma[i] = 1.0 / (4.0 * p->gamma[i]);
+        h.p_eq[i] = p->p_eq[i];
+        h.q_eq[i] = p->q_eq[i];
+        sg += p->gamma[i];
+    }
+    for (int i = 0; i < F; ++i)
+        for (int j = i + 1; j < F; ++j) {
+            h.lam[i * FMAX + j] = p->lambda[i * F + j];
+            h.lam[j * FMAX + i] = p->lambda[i * F + j];
+        }
+    // fourth-order triple jump: w1 = 1/(2 - 2^(1/3)), w0 = -2^(1/3) w1
+    const double cbrt2 = cbrt(2.0);
+    const double w1 = 1.0 / (2.0 - cbrt2);
+    const double w0 = -cbrt2 / (2.0 - cbrt2);
+    const double dco[4] = {0.5 * w1, 0.5 * (w0 + w1), 0.5 * (w0 + w1), 0.5 * w1};
+    const double cco[3] = {w1, w0, w1};
+    for (int s = 0; s < 4; ++s) h.hd[s] = dco[s] * p->dt;
+    for (int s = 0; s < 3; ++s) h.hc[s] = cco[s] * p->dt;
+    h.dt = p->dt;
+    h.sum_gamma = sg;
+    h.det_tol = p->det_tol;
+    h.F_log_2pi = (double)F * log(2.0 * M_PI);
+    h.e_min = p->e_min;
+    h.e_max = p->e_max;
+
+    hipError_t e = hipSetDevice(device);
+    if (e != hipSuccess) {
+        delete c;
+        return SCIVR_EDEVICE;
+    }
+    const int64_t NP = c->npad;
+    const int64_t G2 = 4ll * F * F;
+    hipError_t ea = hipSuccess;
+    auto A = [&](hipError_t r) {
+        if (r != hipSuccess && ea == hipSuccess) ea = r;
+    };
+    A(dalloc(&c->d_prob, 1));
+    A(dalloc(&c->d_p0, F * NP));
+    A(dalloc(&c->d_q0, F * NP));
+    A(dalloc(&c->d_logrho, NP));
+    A(dalloc(&c->d_p, F * NP));
+    A(dalloc(&c->d_q, F * NP));
+    A(dalloc(&c->d_scal, NSCAL * NP));
+    A(dalloc(&c->d_M, G2 * NP));
+    A(dalloc(&c->d_amp, (int64_t)c->nt_alloc * NP));
+    A(dalloc(&c->d_phase, (int64_t)c->nt_alloc * c->kpad));
+    A(dalloc(&c->d_weight, NP));
+    A(dalloc(&c->d_part_spec, (int64_t)c->row_tiles * c->kpad));
+    A(dalloc(&c->d_part_contrib, (int64_t)(c->kpad / 64) * NP));
+    A(dalloc(&c->d_contrib, NP));
+    A(dalloc(&c->d_total, c->n_energies));
+    A(dalloc(&c->d_ngood, 1));
+    if (ea != hipSuccess) {
+        const bool oom = (ea == hipErrorOutOfMemory || ea == hipErrorMemoryAllocation);
+        free_all(c);
+        delete c;
+        (void)hipGetLastError();
+        return oom ? SCIVR_ENOMEM : SCIVR_EDEVICE;
+    }
+    hipStream_t s0 = nullptr;
+    e = hipMemcpy(c->d_prob, &h, sizeof h, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = launch_fill_zero((double *)c->d_amp, 2ll * c->nt_alloc * NP, s0);
+    if (e == hipSuccess) e = launch_fill_zero(c->d_logrho, NP, s0);
+    if (e == hipSuccess) e = launch_fill_zero(c->d_scal, NSCAL * NP, s0);
+    if (e == hipSuccess) e = launch_fill_zero(c->d_total, c->n_energies, s0);
+    if (e == hipSuccess) e = launch_fill_zero((double *)c->d_ngood, 1, s0);
+    if (e == hipSuccess)
+        e = launch_phase_table(p->e_min, p->e_max, p->n_energies, c->kpad, c->nt, c->nt_alloc, p->dt, c->d_phase, s0);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) {
+        free_all(c);
+        delete c;
+        return SCIVR_EDEVICE;
+    }
+    *out = c;
+    return SCIVR_OK;
+}
+
+void scivr_destroy(scivr_ctx *ctx)
+{
+    if (!ctx) return;
+    if (hipSetDevice(ctx->device) == hipSuccess) (void)hipDeviceSynchronize();
+    free_all(ctx);
+    delete ctx;
+}
+
+scivr_status scivr_sample_husimi(scivr_ctx *ctx, uint64_t seed, uint64_t first_index, int64_t n_traj, void *stream)
+{
+    CHECK_CTX(ctx);
+    if (n_traj < 1 || n_traj > ctx->max_traj)
+        return fail(ctx, SCIVR_EINVAL, "n_traj %lld outside [1, %lld]", (long long)n_traj, (long long)ctx->max_traj);
+    hipStream_t s = (hipStream_t)stream;
+    Timed tm(ctx, s, 0);
+    HIPCALL(ctx, launch_sample_husimi(ctx->d_prob, ctx->F, seed, first_index, n_traj, ctx->npad, ctx->d_p0,
+                                      ctx->d_q0, ctx->d_logrho, s));
+    tm.done();
+    ctx->n_traj = n_traj;
+    ctx->steps_done = 0;
+    ctx->have_initial = true;
+    ctx->accumulated = false;
+    return SCIVR_OK;
+}
+
+scivr_status scivr_set_initial(scivr_ctx *ctx, int64_t n_traj, const double *p0, const double *q0,
+                               const double *log_density, int32_t mem_kind, void *stream)
+{
+    CHECK_CTX(ctx);
+    if (n_traj < 1 || n_traj > ctx->max_traj)
+        return fail(ctx, SCIVR_EINVAL, "n_traj %lld outside [1, %lld]", (long long)n_traj, (long long)ctx->max_traj);
+    if (!p0 || !q0 || !log_density) return fail(ctx, SCIVR_EINVAL, "null initial-condition pointer");
+    if (mem_kind != SCIVR_MEM_HOST && mem_kind != SCIVR_MEM_DEVICE)
+        return fail(ctx, SCIVR_EINVAL, "bad mem_kind %d", mem_kind);
+    hipStream_t s = (hipStream_t)stream;
+    const hipMemcpyKind kind = mem_kind == SCIVR_MEM_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
+    const size_t row = (size_t)n_traj * sizeof(double), pitch = (size_t)ctx->npad * sizeof(double);
+    HIPCALL(ctx, hipMemcpy2DAsync(ctx->d_p0, pitch, p0, row, row, ctx->F, kind, s));
+    HIPCALL(ctx, hipMemcpy2DAsync(ctx->d_q0, pitch, q0, row, row, ctx->F, kind, s));
+    HIPCALL(ctx, hipMemcpyAsync(ctx->d_logrho, log_density, row, kind, s));
+    if (mem_kind == SCIVR_MEM_HOST) HIPCALL(ctx, hipStreamSynchronize(s));
+    ctx->n_traj = n_traj;
+    ctx->steps_done = 0;
+    ctx->have_initial = true;
+    ctx->accumulated = false;
+    return SCIVR_OK;
+}
+
+scivr_status scivr_propagate(scivr_ctx *ctx, int32_t step_begin, int32_t step_end, void *stream)
+{
+    CHECK_CTX(ctx);
+    if (!ctx->have_initial) return fail(ctx, SCIVR_ESTATE, "propagate before initial conditions");
+    if (step_begin != ctx->steps_done)
+        return fail(ctx, SCIVR_ESTATE, "step_begin %d but %d steps done", step_begin, ctx->steps_done);
+    if (step_end <= step_begin || step_end > ctx->n_steps)
+        return fail(ctx, SCIVR_EINVAL, "step_end %d outside (%d, %d]", step_end, step_begin, ctx->n_steps);
+    hipStream_t s = (hipStream_t)stream;
+    TrajArgs a;
+    a.prob = ctx->d_prob;
+    a.p0 = ctx->d_p0;
+    a.q0 = ctx->d_q0;
+    a.p = ctx->d_p;
+    a.q = ctx->d_q;
+    a.scal = ctx->d_scal;
+    a.Mst = ctx->d_M;
+    a.amp = ctx->d_amp;
+    a.n = ctx->n_traj;
+    a.npad = ctx->npad;
+    a.step_begin = step_begin;
+    a.step_end = step_end;
+    a.n_steps = ctx->n_steps;
+    a.check_every = ctx->check_every;
+    Timed tm(ctx, s, 1);
+    HIPCALL(ctx, launch_traj_fp64(ctx->F, a, s));
+    tm.done();
+    ctx->steps_done = step_end;
+    ctx->accumulated = false;
+    return SCIVR_OK;
+}
+
+scivr_status scivr_accumulate_spectrum(scivr_ctx *ctx, void *stream)
+{
+    CHECK_CTX(ctx);
+    if (!ctx->have_initial || ctx->steps_done != ctx->n_steps)
+        return fail(ctx, SCIVR_ESTATE, "accumulate needs a fully propagated batch (%d of %d steps)", ctx->steps_done,
+                    ctx->n_steps);
+    if (ctx->accumulated) return fail(ctx, SCIVR_ESTATE, "batch already accumulated");
+    hipStream_t s = (hipStream_t)stream;
+    HIPCALL(ctx, launch_weights(ctx->d_scal + SC_GOOD * ctx->npad, ctx->d_logrho, ctx->host_prob.F_log_2pi,
+                                ctx->n_traj, ctx->npad, ctx->d_weight, ctx->d_ngood, s));
+    GemmArgs g;
+    g.amp = ctx->d_amp;
+    g.phase = ctx->d_phase;
+    g.weight = ctx->d_weight;
+    g.part_spec = ctx->d_part_spec;
+    g.part_contrib = ctx->d_part_contrib;
+    g.npad = ctx->npad;
+    g.kpad = ctx->kpad;
+    g.nt_pad = ctx->nt_pad;
+    // only the row tiles that hold trajectories of this batch
+    g.row_tiles = (int32_t)((ctx->n_traj + GEMM_BM - 1) / GEMM_BM);
+    g.col_tiles = ctx->col_tiles;
+    {
+        Timed tm(ctx, s, 2);
+        HIPCALL(ctx, launch_fourier_fp64(g, s));
+        tm.done();
+    }
+    {
+        Timed tm(ctx, s, 3);
+        HIPCALL(ctx, launch_spectrum_reduce(ctx->d_part_spec, g.row_tiles, ctx->n_energies, ctx->kpad, ctx->d_total,
+                                            s));
+        HIPCALL(ctx, launch_contrib_reduce(ctx->d_part_contrib, ctx->kpad / 64, ctx->d_weight, ctx->n_traj,
+                                           ctx->npad, ctx->d_contrib, s));
+        tm.done();
+    }
+    ctx->n_total += ctx->n_traj;
+    ctx->accumulated = true;
+    return SCIVR_OK;
+}
+
+scivr_status scivr_read_spectrum(scivr_ctx *ctx, double *I_host, int64_t *n_good, int64_t *n_total)
+{
+    CHECK_CTX(ctx);
+    HIPCALL(ctx, hipDeviceSynchronize());
+    unsigned long long ng = 0;
+    HIPCALL(ctx, hipMemcpy(&ng, ctx->d_ngood, sizeof ng, hipMemcpyDeviceToHost));
+    if (n_good) *n_good = (int64_t)ng;
+    if (n_total) *n_total = ctx->n_total;
+    if (I_host) {
+        if (ng == 0) {
+            for (int k = 0; k < ctx->n_energies; ++k) I_host[k] = 0.0;
+        } else {
+            HIPCALL(ctx, hipMemcpy(I_host, ctx->d_total, sizeof(double) * ctx->n_energies, hipMemcpyDeviceToHost));
+            const double T = (double)ctx->n_steps * ctx->dt;
+            const double scale = ctx->dt * ctx->dt / (2.0 * M_PI * T * (double)ng);
+            for (int k = 0; k < ctx->n_energies; ++k) I_host[k] *= scale;
+        }
+    }
+    return ng == 0 ? SCIVR_ENOGOOD : SCIVR_OK;
+}
+
+scivr_status scivr_reset_spectrum(scivr_ctx *ctx, void *stream)
+{
+    CHECK_CTX(ctx);
+    hipStream_t s = (hipStream_t)stream;
+    HIPCALL(ctx, launch_fill_zero(ctx->d_total, ctx->n_energies, s));
+    HIPCALL(ctx, launch_fill_zero((double *)ctx->d_ngood, 1, s));
+    ctx->n_total = 0;
+    return SCIVR_OK;
+}
+
+scivr_status scivr_batch_info(const scivr_ctx *ctx, int64_t *n_traj, int32_t *steps_done)
+{
+    if (!ctx) return SCIVR_EINVAL;
+    if (n_traj) *n_traj = ctx->have_initial ? ctx->n_traj : 0;
+    if (steps_done) *steps_done = ctx->steps_done;
+    return SCIVR_OK;
+}
+
+static scivr_status copy_rows(scivr_ctx *ctx, double *dst, const double *src, int rows)
+{
+    const size_t row = (size_t)ctx->n_traj * sizeof(double), pitch = (size_t)ctx->npad * sizeof(double);
+    HIPCALL(ctx, hipMemcpy2D(dst, row, src, pitch, row, rows, hipMemcpyDeviceToHost));
+    return SCIVR_OK;
+}
+
+scivr_status scivr_read_initial(scivr_ctx *ctx, double *p0, double *q0, double *log_density)
+{
+    CHECK_CTX(ctx);
+    if (!ctx->have_initial) return fail(ctx, SCIVR_ESTATE, "no initial conditions");
+    HIPCALL(ctx, hipDeviceSynchronize());
+    scivr_status st;
+    if (p0 && (st = copy_rows(ctx, p0, ctx->d_p0, ctx->F)) != SCIVR_OK) return st;
+    if (q0 && (st = copy_rows(ctx, q0, ctx->d_q0, ctx->F)) != SCIVR_OK) return st;
+    if (log_density && (st = copy_rows(ctx, log_density, ctx->d_logrho, 1)) != SCIVR_OK) return st;
+    return SCIVR_OK;
+}
+
+scivr_status scivr_read_state(scivr_ctx *ctx, double *p, double *q, double *S, double *phi, double *M, uint8_t *good,
+                              double *detM, double *maxdev)
+{
+    CHECK_CTX(ctx);
+    if (!ctx->have_initial || ctx->steps_done == 0) return fail(ctx, SCIVR_ESTATE, "no propagated state");
+    HIPCALL(ctx, hipDeviceSynchronize());
+    const int64_t n = ctx->n_traj, NP = ctx->npad;
+    scivr_status st;
+    if (p && (st = copy_rows(ctx, p, ctx->d_p, ctx->F)) != SCIVR_OK) return st;
+    if (q && (st = copy_rows(ctx, q, ctx->d_q, ctx->F)) != SCIVR_OK) return st;
+    if (S && (st = copy_rows(ctx, S, ctx->d_scal + SC_S * NP, 1)) != SCIVR_OK) return st;
+    if (phi && (st = copy_rows(ctx, phi, ctx->d_scal + SC_PHI * NP, 1)) != SCIVR_OK) return st;
+    if (detM && (st = copy_rows(ctx, detM, ctx->d_scal + SC_DETM * NP, 1)) != SCIVR_OK) return st;
+    if (maxdev && (st = copy_rows(ctx, maxdev, ctx->d_scal + SC_MAXDEV * NP, 1)) != SCIVR_OK) return st;
+    if (good) {
+        std::vector<double> g(n);
+        if ((st = copy_rows(ctx, g.data(), ctx->d_scal + SC_GOOD * NP, 1)) != SCIVR_OK) return st;
+        for (int64_t j = 0; j < n; ++j) good[j] = g[j] != 0.0 ? 1 : 0;
+    }
+    if (M) {
+        const int G = 2 * ctx->F;
+        std::vector<double> buf((size_t)G * G * n);
+        if ((st = copy_rows(ctx, buf.data(), ctx->d_M, G * G)) != SCIVR_OK) return st;
+        for (int64_t j = 0; j < n; ++j)
+            for (int e = 0; e < G * G; ++e) M[j * G * G + e] = buf[(size_t)e * n + j];
+    }
+    return SCIVR_OK;
+}
+
+scivr_status scivr_read_amplitudes(scivr_ctx *ctx, int64_t j0, int64_t count, double *amp)
+{
+    CHECK_CTX(ctx);
+    if (!amp || j0 < 0 || count < 1 || j0 + count > ctx->n_traj)
+        return fail(ctx, SCIVR_EINVAL, "amplitude range [%lld, %lld) outside the batch", (long long)j0,
+                    (long long)(j0 + count));
+    HIPCALL(ctx, hipDeviceSynchronize());
+    const int nt = ctx->nt;
+    std::vector<double2> buf((size_t)nt * count);
+    HIPCALL(ctx, hipMemcpy2D(buf.data(), count * sizeof(double2), ctx->d_amp + j0, ctx->npad * sizeof(double2),
+                             count * sizeof(double2), nt, hipMemcpyDeviceToHost));
+    for (int64_t j = 0; j < count; ++j)
+        for (int c = 0; c < nt; ++c) {
+            amp[(j * nt + c) * 2] = buf[(size_t)c * count + j].x;
+            amp[(j * nt + c) * 2 + 1] = buf[(size_t)c * count + j].y;
+        }
+    return SCIVR_OK;
+}
+
+scivr_status scivr_read_contributions(scivr_ctx *ctx, double *c)
+{
+    CHECK_CTX(ctx);
+    if (!c) return fail(ctx, SCIVR_EINVAL, "null output");
+    if (!ctx->accumulated) return fail(ctx, SCIVR_ESTATE, "batch not accumulated");
+    HIPCALL(ctx, hipDeviceSynchronize());
+    HIPCALL(ctx, hipMemcpy(c, ctx->d_contrib, sizeof(double) * ctx->n_traj, hipMemcpyDeviceToHost));
+    return SCIVR_OK;
+}
+
+scivr_status scivr_timing_enable(scivr_ctx *ctx, int32_t on)
+{
+    CHECK_CTX(ctx);
+    HIPCALL(ctx, hipDeviceSynchronize());
+    for (auto &e : ctx->events) {
+        (void)hipEventDestroy(e.a);
+        (void)hipEventDestroy(e.b);
+    }
+    ctx->events.clear();
+    ctx->timing = on != 0;
+    return SCIVR_OK;
+}
+
+scivr_status scivr_kernel_times(scivr_ctx *ctx, int64_t *launches, double *ms)
+{
+    CHECK_CTX(ctx);
+    for (int k = 0; k < SCIVR_KERNEL_KINDS; ++k) {
+        if (launches) launches[k] = 0;
+        if (ms) ms[k] = 0.0;
+    }
+    for (auto &e : ctx->events) {
+        HIPCALL(ctx, hipEventSynchronize(e.b));
+        float t = 0.f;
+        HIPCALL(ctx, hipEventElapsedTime(&t, e.a, e.b));
+        if (launches) launches[e.kind] += 1;
+        if (ms) ms[e.kind] += (double)t;
+    }
+    for (auto &e : ctx->events) {
+        (void)hipEventDestroy(e.a);
+        (void)hipEventDestroy(e.b);
+    }
+    ctx->events.clear();
+    return SCIVR_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,193 @@
+// Small kernels around the two hot ones: Husimi sampling, the time x energy
+// phase table, per-trajectory weights, deterministic reductions.
+#include <math.h>
+
+#include "scivr_internal.h"
+
+namespace scivr {
+namespace {
+
+// Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two 64x64->128
+// multiplications with key bumps by the golden-ratio and sqrt(3)-1 Weyl constants.
+__device__ inline void philox4x64_10(uint64_t c0, uint64_t c1, uint64_t c2, uint64_t c3, uint64_t k0, uint64_t k1,
+                                     uint64_t out[4])
+{
+    const uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
+    const uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        if (r > 0) {
+            k0 += W0;
+            k1 += W1;
+        }
+        const uint64_t hi0 = __umul64hi(M0, c0), lo0 = M0 * c0;
+        const uint64_t hi1 = __umul64hi(M1, c2), lo1 = M1 * c2;
+        const uint64_t n0 = hi1 ^ c1 ^ k0;
+        const uint64_t n2 = hi0 ^ c3 ^ k1;
+        c0 = n0;
+        c1 = lo1;
+        c2 = n2;
+        c3 = lo0;
+    }
+    out[0] = c0;
+    out[1] = c1;
+    out[2] = c2;
+    out[3] = c3;
+}
+
+__device__ inline double u01(uint64_t x) { return ((double)(x >> 11) + 0.5) * (1.0 / 9007199254740992.0); }
+
+// One thread per trajectory: 2F normals from ceil(2F/4) Philox blocks with
+// counter (index, block, 0, 0) and key (seed, 0), Box-Muller on uniform pairs;
+// q = q_eq + xi / sqrt(gamma), p = p_eq + eta sqrt(gamma), ln rho of the
+// product Gaussian (Husimi density of chi).
+__global__ void sample_husimi_kernel(const ProblemDev *__restrict__ P, int F, uint64_t seed, uint64_t first,
+                                     int64_t n, int64_t npad, double *p0, double *q0, double *logrho)
+{
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    const double two_pi = 6.283185307179586476925286766559;
+    double sq = 0.0;
+    const int count = 2 * F;
+    for (int b = 0; 4 * b < count; ++b) {
+        uint64_t r[4];
+        philox4x64_10(first + (uint64_t)j, (uint64_t)b, 0, 0, seed, 0, r);
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int i0 = 4 * b + 2 * h;
+            if (i0 >= count) break;
+            const double rad = sqrt(-2.0 * log(u01(r[2 * h])));
+            double s, co;
+            sincos(two_pi * u01(r[2 * h + 1]), &s, &co);
+            const double xi = rad * co, eta = rad * s;  // normals i0 and i0 + 1
+            const int mode = i0 / 2;
+            q0[mode * npad + j] = P->q_eq[mode] + xi / P->sqrt_gamma[mode];
+            p0[mode * npad + j] = P->p_eq[mode] + eta * P->sqrt_gamma[mode];
+            sq += xi * xi + eta * eta;
+        }
+    }
+    logrho[j] = -P->F_log_2pi - 0.5 * sq;
+}
+
+// phase[c][k] = exp(i E_k c dt), E_k = e_min + k (e_max - e_min)/(K - 1); zero padding.
+__global__ void phase_table_kernel(double e_min, double e_max, int K, int kpad, int nt, int nt_pad, double dt,
+                                   double2 *phase)
+{
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (int64_t)nt_pad * kpad) return;
+    const int c = (int)(idx / kpad), k = (int)(idx % kpad);
+    double2 v;
+    v.x = 0.0;
+    v.y = 0.0;
+    if (c < nt && k < K) {
+        const double E = e_min + (double)k * (e_max - e_min) / (double)(K - 1);
+        double s, co;
+        sincos(E * ((double)c * dt), &s, &co);
+        v.x = co;
+        v.y = s;
+    }
+    phase[idx] = v;
+}
+
+// weight_j = good_j exp(-ln rho_j - F ln 2 pi) for j < n, 0 in the padding; counts good.
+__global__ void weights_kernel(const double *__restrict__ good_row, const double *__restrict__ logrho,
+                               double F_log_2pi, int64_t n, int64_t npad, double *weight,
+                               unsigned long long *n_good)
+{
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    bool g = false;
+    if (j < npad) {
+        double w = 0.0;
+        if (j < n && good_row[j] != 0.0) {
+            w = exp(-logrho[j] - F_log_2pi);
+            g = true;
+        }
+        weight[j] = w;
+    }
+    const unsigned long long cnt = __popcll(__ballot(g));
+    if ((threadIdx.x & 63) == 0 && cnt) atomicAdd(n_good, cnt);
+}
+
+// total[k] += sum over row tiles of part[rt][k], in row-tile order (deterministic).
+__global__ void spectrum_reduce_kernel(const double *__restrict__ part, int row_tiles, int K, int kpad,
+                                       double *total)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= K) return;
+    double s = 0.0;
+    for (int rt = 0; rt < row_tiles; ++rt) s += part[(int64_t)rt * kpad + k];
+    total[k] += s;
+}
+
+// contrib[j] = weight_j * sum over column tiles of part[ct][j].
+__global__ void contrib_reduce_kernel(const double *__restrict__ part, int ctiles, const double *__restrict__ weight,
+                                      int64_t n, int64_t npad, double *contrib)
+{
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    double s = 0.0;
+    for (int ct = 0; ct < ctiles; ++ct) s += part[(int64_t)ct * npad + j];
+    contrib[j] = weight[j] * s;
+}
+
+__global__ void fill_zero_kernel(double *p, int64_t count)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) p[i] = 0.0;
+}
+
+inline unsigned blocks_for(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+}  // namespace
+
+hipError_t launch_sample_husimi(const ProblemDev *P, int F, uint64_t seed, uint64_t first, int64_t n, int64_t npad,
+                                double *p0, double *q0, double *logrho, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(sample_husimi_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, P, F, seed, first, n, npad,
+                       p0, q0, logrho);
+    return hipGetLastError();
+}
+
+hipError_t launch_phase_table(double e_min, double e_max, int K, int kpad, int nt, int nt_pad, double dt,
+                              double2 *phase, hipStream_t s)
+{
+    const int64_t total = (int64_t)nt_pad * kpad;
+    hipLaunchKernelGGL(phase_table_kernel, dim3(blocks_for(total, 256)), dim3(256), 0, s, e_min, e_max, K, kpad, nt,
+                       nt_pad, dt, phase);
+    return hipGetLastError();
+}
+
+hipError_t launch_weights(const double *scal_good_row, const double *logrho, double F_log_2pi, int64_t n,
+                          int64_t npad, double *weight, unsigned long long *n_good, hipStream_t s)
+{
+    hipLaunchKernelGGL(weights_kernel, dim3(blocks_for(npad, 256)), dim3(256), 0, s, scal_good_row, logrho, F_log_2pi,
+                       n, npad, weight, n_good);
+    return hipGetLastError();
+}
+
+hipError_t launch_spectrum_reduce(const double *part_spec, int row_tiles, int K, int kpad, double *total,
+                                  hipStream_t s)
+{
+    hipLaunchKernelGGL(spectrum_reduce_kernel, dim3(blocks_for(K, 256)), dim3(256), 0, s, part_spec, row_tiles, K,
+                       kpad, total);
+    return hipGetLastError();
+}
+
+hipError_t launch_contrib_reduce(const double *part_contrib, int ctiles, const double *weight, int64_t n,
+                                 int64_t npad, double *contrib, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(contrib_reduce_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, part_contrib, ctiles, weight,
+                       n, npad, contrib);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_zero(double *p, int64_t count, hipStream_t s)
+{
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(fill_zero_kernel, dim3(blocks_for(count, 256)), dim3(256), 0, s, p, count);
+    return hipGetLastError();
+}
+
+}  // namespace scivr

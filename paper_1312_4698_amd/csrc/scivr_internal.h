@@ -1,0 +1,69 @@
+// Internal declarations shared by the HIP sources of libscivr (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace scivr {
+
+constexpr int FMAX = 16;
+
+// Tile sizes of the Fourier GEMM: a workgroup covers GEMM_BM trajectories x
+// GEMM_BN energies; the time axis is consumed GEMM_BK samples per MFMA step.
+constexpr int GEMM_BM = 128;
+constexpr int GEMM_BN = 128;
+constexpr int GEMM_BK = 4;
+
+// Scalar per-trajectory state rows, structure of arrays [NSCAL][npad].
+enum ScalarRow { SC_S = 0, SC_THETA, SC_RPREV, SC_PHI, SC_GOOD, SC_DETM, SC_MAXDEV, NSCAL };
+
+// Trajectory-independent constants, read with uniform (scalar) loads.
+struct ProblemDev {
+    double k[FMAX], D[FMAX], a[FMAX];
+    double gamma[FMAX], sqrt_gamma[FMAX], inv_sqrt_gamma[FMAX], inv4gamma[FMAX];
+    double p_eq[FMAX], q_eq[FMAX];
+    double lam[FMAX * FMAX];  // symmetric, zero diagonal, row stride FMAX
+    double hd[4];             // drift lengths d_s * dt
+    double hc[3];             // kick lengths c_s * dt
+    double dt, sum_gamma, det_tol;
+    double F_log_2pi;         // F ln(2 pi)
+    double e_min, e_max;
+};
+
+struct TrajArgs {
+    const ProblemDev *prob;
+    const double *p0, *q0;  // [F][npad]
+    double *p, *q;          // [F][npad] state
+    double *scal;           // [NSCAL][npad]
+    double *Mst;            // [(2F)^2][npad], element r*2F + c
+    double2 *amp;           // [nt_pad][npad]
+    int64_t n, npad;
+    int32_t step_begin, step_end, n_steps, check_every;
+};
+
+struct GemmArgs {
+    const double2 *amp;     // [nt_pad][npad]
+    const double2 *phase;   // [nt_pad][kpad]
+    const double *weight;   // [npad] good_j * w_j
+    double *part_spec;      // [npad / GEMM_BM][kpad]
+    double *part_contrib;   // [kpad / 64][npad]
+    int64_t npad;
+    int32_t kpad, nt_pad;
+    int32_t row_tiles, col_tiles;
+};
+
+hipError_t launch_traj_fp64(int F, const TrajArgs &a, hipStream_t s);
+hipError_t launch_sample_husimi(const ProblemDev *P, int F, uint64_t seed, uint64_t first, int64_t n, int64_t npad,
+                                double *p0, double *q0, double *logrho, hipStream_t s);
+hipError_t launch_phase_table(double e_min, double e_max, int K, int kpad, int nt, int nt_pad, double dt,
+                              double2 *phase, hipStream_t s);
+hipError_t launch_weights(const double *scal, const double *logrho, double F_log_2pi, int64_t n, int64_t npad,
+                          double *weight, unsigned long long *n_good, hipStream_t s);
+hipError_t launch_fourier_fp64(const GemmArgs &a, hipStream_t s);
+hipError_t launch_spectrum_reduce(const double *part_spec, int row_tiles, int K, int kpad, double *total,
+                                  hipStream_t s);
+hipError_t launch_contrib_reduce(const double *part_contrib, int ctiles, const double *weight, int64_t n,
+                                 int64_t npad, double *contrib, hipStream_t s);
+hipError_t launch_fill_zero(double *p, int64_t count, hipStream_t s);
+
+}  // namespace scivr
