@@ -1,0 +1,211 @@
+"""Benchmark of the TA-SC-IVR power-spectrum hot path on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload F9_fp64]
+
+One step is one pass of the whole hot path over one batch of synthetic input:
+Husimi sampling of the batch on the GPU, propagation of every trajectory over
+all time steps (symplectic step with Hessian, monodromy, action, prefactor
+phase, stability monitor, amplitudes) and the Fourier GEMM with its weighted
+|A|^2 reduction into the spectrum.  Inputs (the problem constants) are
+resident in HBM before the timed region.  The metric is trajectory-steps/s:
+n_traj * n_steps per step / seconds per step.
+
+The JSON line also carries the roofline of the dominant kernel (the
+trajectory kernel, bound by FP64 vector ALU), its per-launch duration from HIP
+events recorded by the library around each launch on its stream, the HBM
+traffic measured with rocprofv3 counters when a matching summary is present
+under profiles/, and the oracle timed on a bounded sample on the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import re
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+FP64_VALU_PEAK_TFLOPS = 78.6   # MI355X FP64 vector: 256 CU x 2.4 GHz x 128 flop/clk
+FP64_MFMA_PEAK_TFLOPS = 78.6   # MI355X FP64 matrix (dense)
+HBM_PEAK_GBS = 8000.0
+
+
+def traj_flops_per_step(F: int) -> float:
+    """Algorithmic FP64 flops of one trajectory-step (FMA = 2), transcendentals excluded.
+
+    drifts 4 x (2F^2 FMA on the tangent q-rows + 5F + 2), kicks 3 x (H M_q: 2F^3 FMA,
+    potential/gradient/Hessian 2F^2 + 12F, momentum and action 2F + 2), det(M) by LU
+    (2/3)(2F)^3, prefactor matrix 8F^2, complex LU of A (8/3)F^3, amplitude and
+    phase 12F + 10.
+    """
+    drift = 4 * (4 * F * F + 5 * F + 2)
+    kick = 3 * (4 * F ** 3 + 2 * F * F + 14 * F + 2)
+    detm = (2.0 / 3.0) * (2 * F) ** 3
+    pref = 8 * F * F
+    deta = (8.0 / 3.0) * F ** 3
+    amp = 12 * F + 10
+    return float(drift + kick + detm + pref + deta + amp)
+
+
+def fourier_flops(n_traj: int, n_times: int, K: int) -> float:
+    """8 flops per complex multiply-add of amp[j][c] exp(i E_k c dt)."""
+    return 8.0 * n_traj * n_times * K
+
+
+def _source_hash(*names):
+    h = hashlib.sha256()
+    for nm in names:
+        with open(os.path.join(ROOT, "paper_1312_4698_amd", "csrc", nm), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def _profile_traffic(kernel_prefix: str, src_hash: str):
+    """HBM bytes per launch from a committed rocprofv3 counter summary, if it
+    was taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", "traj_fp64_F9_N262144_counters.txt")
+    if not os.path.exists(path):
+        return None
+    txt = open(path).read()
+    m = re.search(r"source_hash:\s*(\w+)", txt)
+    b = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", txt)
+    if not m or not b or m.group(1) != src_hash:
+        return None
+    return float(b.group(1))
+
+
+def cpu_baseline(prob, n_sample: int, seed: int):
+    """The oracle as it stands, on all host cores, over a bounded sample."""
+    from oracle import oracle as O
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    p0, q0, lr = O.sample_husimi(prob, seed, n_sample)
+    t0 = time.perf_counter()
+    O.run(prob, p0, q0, lr, want_state=False, want_contrib=False, n_threads=threads)
+    dt = time.perf_counter() - t0
+    return {"value": n_sample * prob.n_steps / dt, "unit": "trajectory-steps/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"{n_sample} trajectories of the same workload (all {prob.n_steps} steps, "
+                      f"{prob.n_energies} energies), {dt:.1f} s wall"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="F9_fp64")
+    ap.add_argument("--n-traj", type=int, default=0, help="override the trajectory count")
+    ap.add_argument("--cpu-sample", type=int, default=512, help="oracle trajectories for the CPU baseline (0: skip)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; the path shards by trajectory index "
+                                   "(see DESIGN.md) but no multi-GPU run is provided", "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import torch
+    from paper_1312_4698_amd import inputs, scivr
+
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU visible"}))
+        sys.exit(1)
+    prob, n = inputs.workload(args.workload)
+    if args.n_traj:
+        n = args.n_traj
+    stream = torch.cuda.current_stream()
+    ctx = scivr.Context(prob, max_traj=n)
+    print(f"[bench] {args.workload}: F={prob.F} n={n} steps={prob.n_steps} K={prob.n_energies}", file=sys.stderr,
+          flush=True)
+
+    def one_step(i):
+        ctx.sample_husimi(seed=1000 + i, n_traj=n, stream=stream)
+        ctx.propagate(0, prob.n_steps, stream=stream)
+        ctx.accumulate(stream=stream)
+
+    for i in range(args.warmup):
+        one_step(i)
+        print(f"[bench] warmup {i} done", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    ctx.reset_spectrum(stream=stream)
+    ctx.timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        one_step(args.warmup + i)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kt = ctx.kernel_times()
+    I, n_good, n_total = ctx.read_spectrum()
+    print(f"[bench] timed {args.steps} steps in {wall:.3f} s; kernels {kt}", file=sys.stderr, flush=True)
+
+    ms_step = wall / args.steps * 1e3
+    traj_steps = n * prob.n_steps
+    value = traj_steps / (wall / args.steps)
+    n_tr, ms_tr = kt["trajectory"]
+    n_fo, ms_fo = kt["fourier"]
+    t_launch = ms_tr / max(n_tr, 1) / 1e3
+    fl_launch = traj_flops_per_step(prob.F) * traj_steps
+    achieved = fl_launch / t_launch / 1e12
+    src_hash = _source_hash("traj_fp64.hip")
+    traffic = _profile_traffic("traj_fp64", src_hash)
+    fo_launch = ms_fo / max(n_fo, 1) / 1e3
+    fo_fl = fourier_flops(n, prob.n_steps + 1, prob.n_energies)
+
+    out = {
+        "metric": "trajectory-steps/s at F=9",
+        "value": value,
+        "unit": "trajectory-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"{args.workload}: Morse + quartic coupling, F={prob.F}, {n} Husimi trajectories, "
+                        f"{prob.n_steps} steps of dt={prob.dt} au, {prob.n_energies} energies on "
+                        f"[{prob.e_min}, {prob.e_max}] hartree",
+            "F": prob.F, "n_traj": n, "n_steps": prob.n_steps, "n_energies": prob.n_energies,
+            "precision": "fp64", "parallelism": "single GPU",
+        },
+        "roofline": {
+            "kernel": "traj_fp64_kernel",
+            "bound": "alu",
+            "achieved": achieved,
+            "peak": FP64_VALU_PEAK_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": achieved / FP64_VALU_PEAK_TFLOPS,
+            "traffic": traffic,
+            "launch_ms": t_launch * 1e3,
+            "flops_per_launch": fl_launch,
+            "source_hash": src_hash,
+        },
+        "roofline_fourier": {
+            "kernel": "fourier_fp64_kernel",
+            "bound": "mfma",
+            "achieved": fo_fl / fo_launch / 1e12,
+            "peak": FP64_MFMA_PEAK_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": fo_fl / fo_launch / 1e12 / FP64_MFMA_PEAK_TFLOPS,
+            "launch_ms": fo_launch * 1e3,
+        },
+        "n_good_fraction": n_good / max(n_total, 1),
+        "cpu_baseline": None,
+    }
+    if args.cpu_sample > 0:
+        print(f"[bench] cpu baseline: oracle on {args.cpu_sample} trajectories", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(prob, args.cpu_sample, seed=77)
+    ctx.close()
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()
