@@ -142,6 +142,44 @@ struct Timed {
     }
 };
 
+// Coefficients and reduction constants of the kernel's exp, sincos and atan2.
+// The split constants are pi/2 and ln 2 rounded to a double, then the
+// remainders rounded in turn (from a 80-digit pi by Machin's formula and
+// ln 2 at the same precision).
+void fill_math_consts(MathConsts &m)
+{
+    double f = 1.0;  // n! is exact in double for n <= 18
+    for (int n = 0; n < 14; ++n) {
+        if (n > 0) f *= n;
+        m.exp_c[n] = 1.0 / f;
+    }
+    double fo = 1.0, fe = 1.0;  // (2n+1)!, (2n)!
+    for (int n = 0; n < 10; ++n) {
+        if (n > 0) {
+            fe = fo * (2 * n);
+            fo = fe * (2 * n + 1);
+        }
+        const double sg = (n & 1) ? -1.0 : 1.0;
+        if (n < 9) m.sin_c[n] = sg / fo;
+        m.cos_c[n] = sg / fe;
+    }
+    for (int n = 0; n < 12; ++n) m.atan_c[n] = ((n & 1) ? -1.0 : 1.0) / (2 * n + 1);
+    m.log2e = 0x1.71547652b82fep+0;
+    m.ln2_hi = 0x1.62e42fefa39efp-1;
+    m.ln2_lo = 0x1.abc9e3b39803fp-56;
+    m.two_over_pi = 0x1.45f306dc9c883p-1;
+    m.pio2_1 = 0x1.921fb54442d18p+0;
+    m.pio2_2 = 0x1.1a62633145c07p-54;
+    m.pio2_3 = -0x1.f1976b7ed8fbcp-110;
+    m.pi = 0x1.921fb54442d18p+1;
+    m.pio2 = 0x1.921fb54442d18p+0;
+    m.pio4 = 0x1.921fb54442d18p-1;
+    m.pio8 = 0x1.921fb54442d18p-2;
+    m.tan_pio8 = sqrt(2.0) - 1.0;
+    m.tan_pio16 = tan(m.pi / 16.0);
+    m.tan_3pio16 = tan(3.0 * m.pi / 16.0);
+}
+
 }  // namespace
 
 extern "C" {
@@ -227,10 +265,13 @@ scivr_status scivr_create(const scivr_problem *p, int32_t device, scivr_ctx **ou
     for (int s = 0; s < 3; ++s) h.hc[s] = cco[s] * p->dt;
     h.dt = p->dt;
     h.sum_gamma = sg;
+    h.cos_gdt = cos(sg * p->dt);
+    h.sin_gdt = sin(sg * p->dt);
     h.det_tol = p->det_tol;
     h.F_log_2pi = (double)F * log(2.0 * M_PI);
     h.e_min = p->e_min;
     h.e_max = p->e_max;
+    fill_math_consts(h.mc);
 
     hipError_t e = hipSetDevice(device);
     if (e != hipSuccess) {

@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "scivr_math.h"
+
 namespace scivr {
 
 constexpr int FMAX = 16;
@@ -15,7 +17,7 @@ constexpr int GEMM_BN = 128;
 constexpr int GEMM_BK = 4;
 
 // Scalar per-trajectory state rows, structure of arrays [NSCAL][npad].
-enum ScalarRow { SC_S = 0, SC_THETA, SC_RPREV, SC_PHI, SC_GOOD, SC_DETM, SC_MAXDEV, NSCAL };
+enum ScalarRow { SC_S = 0, SC_THETA, SC_PREV_RE, SC_PREV_IM, SC_PHI, SC_GOOD, SC_DETM, SC_MAXDEV, NSCAL };
 
 // Trajectory-independent constants, read with uniform (scalar) loads.
 struct ProblemDev {
@@ -26,8 +28,10 @@ struct ProblemDev {
     double hd[4];             // drift lengths d_s * dt
     double hc[3];             // kick lengths c_s * dt
     double dt, sum_gamma, det_tol;
+    double cos_gdt, sin_gdt;  // exp(i dt sum gamma)
     double F_log_2pi;         // F ln(2 pi)
     double e_min, e_max;
+    MathConsts mc;            // coefficients of the kernel's exp, sincos, atan2
 };
 
 struct TrajArgs {

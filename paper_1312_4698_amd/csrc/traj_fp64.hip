@@ -35,15 +35,24 @@ template <int F>
 struct alignas(16) GroupLds {
     static constexpr int N2 = 2 * F;
     static constexpr int RS = N2 + 2;  // row stride of the transposed matrix (keeps 16-byte rows)
-    double M[N2 * RS];
-    double piv[2 * N2];                // pivot row (real: N2 values; complex: F (re, im) pairs)
+    double M[N2 * RS];                 // transposed monodromy matrix, row r at r * RS
+    double pivM[N2];                   // pivot row of the real elimination
+    double pivA[N2];                   // pivot row of the complex elimination (re, im interleaved)
     double pg[F + (F & 1)], ph[F + (F & 1)], pv[F + (F & 1)];
-    unsigned long long slot[N2];       // per-step argmax keys
+    unsigned long long slotM[N2];      // per-step argmax keys of the two eliminations
+    unsigned long long slotA[F + (F & 1)];
 };
 
 __device__ inline unsigned long long dbits(double x) { return (unsigned long long)__double_as_longlong(x); }
 
-__device__ inline void wave_sync() { __syncthreads(); }  // workgroups are one wave: orders LDS traffic
+// Workgroups are one wave, and a wave's LDS instructions execute in issue
+// order, so a write by one lane is visible to a later read by another lane of
+// the same wave without waiting; only the compiler must keep the order.
+__device__ inline void lds_order()
+{
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
 
 typedef const __attribute__((address_space(4))) ProblemDev *ConstProblem;
 
@@ -58,131 +67,119 @@ __device__ inline ConstProblem opaque(const ProblemDev *P)
     return (ConstProblem)v;
 }
 
-// det of the N x N matrix whose row `pos` lives in lane-local a[] (lanes with
-// alive == false hold no row).  Partial pivoting on |a|, ties to the lowest
-// position, so the elimination order matches a textbook row-swapping LU.
-template <int N, int F>
-__device__ inline double lu_det_real(double (&a)[N], int pos, bool alive, GroupLds<F> &L)
+// Gaussian elimination with partial pivoting across the lanes of a group.
+// Lane-local a[] is the row at position `pos` (lanes with alive == false hold
+// no row).  Each step takes the column maximum with one LDS atomic max over
+// packed (|a_k|, 63 - pos) keys (ties go to the lowest position, as in a
+// row-swapping LU); only the winning lane then publishes its row into the
+// pivot buffer, which the group reads back as a broadcast.  The row at
+// position k and the pivot swap positions; the sign of the determinant flips
+// when they differ.  Apart from the pivot's store, everything is branch-free.
+template <int N>
+__device__ inline double lu_det_real(double (&a)[N], int pos, bool alive, double *piv, unsigned long long *slot)
 {
-    if (alive) L.slot[pos] = 0ull;
+    if (alive) slot[pos] = 0ull;
     double det = 1.0;
-    wave_sync();
 #pragma unroll
     for (int k = 0; k < N; ++k) {
-        if (alive) {
-            const unsigned long long key = (dbits(fabs(a[k])) & ~63ull) | (unsigned long long)(63 - pos);
-            atomicMax(&L.slot[k], key);
-        }
-        wave_sync();
-        const unsigned long long win = __hip_atomic_load(&L.slot[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        lds_order();
+        if (alive) atomicMax(&slot[k], (dbits(fabs(a[k])) & ~63ull) | (unsigned long long)(63 - pos));
+        lds_order();
+        const unsigned long long win = __hip_atomic_load(&slot[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
         const int ppos = 63 - (int)(win & 63ull);
-        const bool isp = alive && (pos == ppos);
+        const bool isp = alive && pos == ppos;
         if (isp) {
 #pragma unroll
-            for (int jj = k; jj < N; ++jj) L.piv[jj] = a[jj];
+            for (int jj = k; jj < N; ++jj) piv[jj] = a[jj];
         }
-        wave_sync();
-        const double pk = L.piv[k];
-        det *= pk;
-        if (ppos != k) det = -det;
-        if (alive && !isp && pos == k) pos = ppos;
-        if (isp) alive = false;
-        if (alive) {
-            const double l = a[k] / pk;
+        lds_order();
+        const double pk = piv[k];
+        det *= (ppos != k) ? -pk : pk;
+        pos = (alive && pos == k) ? ppos : pos;
+        alive = alive && !isp;
+        if (alive) {  // rows already eliminated (and the pivot) skip the broadcast read
+            const double l = a[k] * rcp_nr(pk);
 #pragma unroll
-            for (int jj = k + 1; jj < N; ++jj) a[jj] = fma(-l, L.piv[jj], a[jj]);
+            for (int jj = k + 1; jj < N; ++jj) a[jj] = fma(-l, piv[jj], a[jj]);
         }
-        wave_sync();
     }
+    lds_order();
     return det;
 }
 
-// Complex version: rows (ar, ai); pivot on |a|^2.
-template <int N, int F>
-__device__ inline void lu_det_complex(double (&ar)[N], double (&ai)[N], int pos, bool alive, GroupLds<F> &L,
-                                      double &dr, double &di)
+// Complex version: rows (ar, ai); pivot on |a_k|^2; the pivot row is stored
+// interleaved (re, im).
+template <int N>
+__device__ inline void lu_det_complex(double (&ar)[N], double (&ai)[N], int pos, bool alive, double *piv,
+                                      unsigned long long *slot, double &dr, double &di)
 {
-    if (alive) L.slot[pos] = 0ull;
+    if (alive) slot[pos] = 0ull;
     double zr = 1.0, zi = 0.0;
-    wave_sync();
 #pragma unroll
     for (int k = 0; k < N; ++k) {
-        if (alive) {
-            const double m2 = fma(ar[k], ar[k], ai[k] * ai[k]);
-            const unsigned long long key = (dbits(m2) & ~63ull) | (unsigned long long)(63 - pos);
-            atomicMax(&L.slot[k], key);
-        }
-        wave_sync();
-        const unsigned long long win = __hip_atomic_load(&L.slot[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        const double m2 = fma(ar[k], ar[k], ai[k] * ai[k]);
+        lds_order();
+        if (alive) atomicMax(&slot[k], (dbits(m2) & ~63ull) | (unsigned long long)(63 - pos));
+        lds_order();
+        const unsigned long long win = __hip_atomic_load(&slot[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
         const int ppos = 63 - (int)(win & 63ull);
-        const bool isp = alive && (pos == ppos);
+        const bool isp = alive && pos == ppos;
         if (isp) {
 #pragma unroll
             for (int jj = k; jj < N; ++jj) {
-                L.piv[2 * jj] = ar[jj];
-                L.piv[2 * jj + 1] = ai[jj];
+                piv[2 * jj] = ar[jj];
+                piv[2 * jj + 1] = ai[jj];
             }
         }
-        wave_sync();
-        const double pr = L.piv[2 * k], pi = L.piv[2 * k + 1];
+        lds_order();
+        const double pr = piv[2 * k], pi = piv[2 * k + 1];
         const double nr = zr * pr - zi * pi;
         const double ni = zr * pi + zi * pr;
-        zr = nr;
-        zi = ni;
-        if (ppos != k) {
-            zr = -zr;
-            zi = -zi;
-        }
-        if (alive && !isp && pos == k) pos = ppos;
-        if (isp) alive = false;
+        zr = (ppos != k) ? -nr : nr;
+        zi = (ppos != k) ? -ni : ni;
+        pos = (alive && pos == k) ? ppos : pos;
+        alive = alive && !isp;
         if (alive) {
-            const double inv = 1.0 / fma(pr, pr, pi * pi);
+            const double inv = rcp_nr(fma(pr, pr, pi * pi));
             const double lr = (ar[k] * pr + ai[k] * pi) * inv;
             const double li = (ai[k] * pr - ar[k] * pi) * inv;
 #pragma unroll
             for (int jj = k + 1; jj < N; ++jj) {
-                const double br = L.piv[2 * jj], bi = L.piv[2 * jj + 1];
+                const double br = piv[2 * jj], bi = piv[2 * jj + 1];
                 ar[jj] = ar[jj] - (lr * br - li * bi);
                 ai[jj] = ai[jj] - (lr * bi + li * br);
             }
         }
-        wave_sync();
     }
+    lds_order();
     dr = zr;
     di = zi;
-}
-
-// Principal value in (-pi, pi] of a difference of two principal arguments
-// (|x| <= 2 pi, or NaN which passes through).
-__device__ inline double wrap_pi(double x)
-{
-    const double pi = 3.14159265358979323846;
-    if (x > pi) x -= 2.0 * pi;
-    else if (x <= -pi) x += 2.0 * pi;
-    return x;
 }
 
 // Waves per SIMD the register allocator must allow (unified 512-register file):
 // small F keeps several waves resident to hide LDS and transcendental latency.
 template <int F>
-constexpr int traj_waves() { return F <= 1 ? 3 : (F <= 12 ? 2 : 1); }
+constexpr int traj_waves() { return F <= 2 ? 4 : (F <= 6 ? 3 : (F <= 12 ? 2 : 1)); }
 
 template <int F>
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(traj_waves<F>(), 8))) traj_fp64_kernel(TrajArgs A, const ProblemDev *__restrict__ P0)
 {
     constexpr int G = 2 * F;
     constexpr int TPW = 64 / G;
-    constexpr int NGRP = (64 + G - 1) / G;
     constexpr int RS = GroupLds<F>::RS;
-    __shared__ GroupLds<F> lds_all[NGRP];
+    __shared__ GroupLds<F> lds_all[TPW];
 
     const int lane = threadIdx.x;
     const int grp = lane / G;
+    // Lanes beyond the last full group own no trajectory.  They leave at once;
+    // nothing below synchronises the workgroup, so the rest of the wave runs on
+    // with them masked off.
+    if (grp >= TPW) return;
     const int c = lane - grp * G;
     const int m = (c < F) ? c : c - F;
     GroupLds<F> &L = lds_all[grp];
     const int64_t j = (int64_t)blockIdx.x * TPW + grp;
-    const bool live = (grp < TPW) && (j < A.n);
+    const bool live = j < A.n;
     const int64_t jr = live ? j : 0;
     const int64_t NP = A.npad;
 
@@ -195,7 +192,7 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(traj_wa
     for (int i = 0; i < F; ++i) lamrow[i] = P->lam[m * FMAX + i];
 
     double p[F], q[F], dp[F], dq[F];
-    double pm, qm, S, theta, rprev, phi, detM, maxdev;
+    double pm, qm, S, theta, prev_r, prev_i, phi, detM, maxdev;
     bool good;
     if (A.step_begin == 0) {
 #pragma unroll
@@ -207,7 +204,8 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(traj_wa
         }
         pm = A.p0[m * NP + jr];
         qm = A.q0[m * NP + jr];
-        S = theta = rprev = phi = 0.0;
+        S = theta = phi = prev_i = 0.0;
+        prev_r = 1.0;  // det(A) = 1 at t = 0
         detM = 1.0;
         maxdev = 0.0;
         good = true;
@@ -223,7 +221,8 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(traj_wa
         qm = A.q[m * NP + jr];
         S = A.scal[SC_S * NP + jr];
         theta = A.scal[SC_THETA * NP + jr];
-        rprev = A.scal[SC_RPREV * NP + jr];
+        prev_r = A.scal[SC_PREV_RE * NP + jr];
+        prev_i = A.scal[SC_PREV_IM * NP + jr];
         phi = A.scal[SC_PHI * NP + jr];
         good = A.scal[SC_GOOD * NP + jr] != 0.0;
         detM = A.scal[SC_DETM * NP + jr];
@@ -241,8 +240,8 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(traj_wa
             ph += 0.5 * dqe * (PP->p_eq[i] + p[i]);
         }
         double s, co;
-        sincos(ph + S + phi, &s, &co);
-        const double mag = exp(ex);
+        dsincos(ph + S + phi, &PP->mc, &s, &co);
+        const double mag = dexp(ex, &PP->mc);
         double2 r;
         r.x = good ? mag * co : 0.0;
         r.y = good ? mag * s : 0.0;
@@ -269,14 +268,15 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(traj_wa
             S = fma(h, kin, S);
             if (s == 3) break;
             // ---- kick ----
-            const double hk = P->hc[s];
+            ConstProblem Pk = opaque(P0);
+            const double hk = Pk->hc[s];
             double q2[F];
 #pragma unroll
             for (int i = 0; i < F; ++i) q2[i] = q[i] * q[i];
             double sm = 0.0;
 #pragma unroll
             for (int i = 0; i < F; ++i) sm = fma(lamrow[i], q2[i], sm);
-            const double e = exp(-am * qm);
+            const double e = dexp(-am * qm, &Pk->mc);
             const double one_e = 1.0 - e;
             const double gm = km * qm + 2.0 * Dm * am * e * one_e + 2.0 * qm * sm;
             const double hm = km + 2.0 * Dm * am * am * e * (2.0 * e - 1.0) + 2.0 * sm;
@@ -286,7 +286,7 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(traj_wa
                 L.ph[c] = hm;
                 L.pv[c] = vm;
             }
-            wave_sync();
+            lds_order();
             double V = 0.0;
 #pragma unroll
             for (int i = 0; i < F; ++i) {
@@ -312,7 +312,7 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(traj_wa
                 }
 #pragma unroll
             for (int i = 0; i < F; ++i) dp[i] = fma(-hk, fma(L.ph[i], dq[i], 4.0 * q[i] * w[i]), dp[i]);
-            wave_sync();
+            lds_order();
         }
 
         const int stp = step + 1;
@@ -324,7 +324,24 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(traj_wa
             L.M[i * RS + c] = dp[i];
             L.M[(F + i) * RS + c] = dq[i];
         }
-        wave_sync();
+        lds_order();
+
+        // prefactor matrix row c: A[c][jj] from M rows c and F+c, then det(A);
+        // only lanes c < F take part (they alone carry the phase, lane 0 writes
+        // the amplitude), the upper half of the group is masked off meanwhile
+        double dAr = 0.0, dAi = 0.0;
+        if (c < F) {
+            double are[F], aim[F];
+#pragma unroll
+            for (int jj = 0; jj < F; ++jj) {
+                const double mpp = L.M[c * RS + jj], mpq = L.M[c * RS + F + jj];
+                const double mqp = L.M[(F + c) * RS + jj], mqq = L.M[(F + c) * RS + F + jj];
+                const double sj = P->sqrt_gamma[jj], isj = P->inv_sqrt_gamma[jj];
+                are[jj] = 0.5 * (sgc * mqq * isj + mpp * sj * isgc);
+                aim[jj] = 0.5 * (-sgc * mqp * sj + mpq * isgc * isj);
+            }
+            lu_det_complex<F>(are, aim, c, true, L.pivA, L.slotA, dAr, dAi);
+        }
 
         // stability monitor |det(M)^2 - 1| on checked steps
         const bool checked = (A.check_every <= 1) || (stp % A.check_every == 0) || (stp == A.n_steps);
@@ -332,34 +349,31 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(traj_wa
             double row[G];
 #pragma unroll
             for (int jj = 0; jj < G; ++jj) row[jj] = L.M[c * RS + jj];
-            wave_sync();
-            const double dM = lu_det_real<G, F>(row, c, true, L);
+            const double dM = lu_det_real<G>(row, c, true, L.pivM, L.slotM);
             const double dev = fabs(dM * dM - 1.0);
             detM = dM;
             if (!(dev <= maxdev)) maxdev = dev;
             if (!(dev <= P->det_tol)) good = false;
         }
 
-        // prefactor matrix row m: A[m][jj] from M rows m and F+m
-        double are[F], aim[F];
-#pragma unroll
-        for (int jj = 0; jj < F; ++jj) {
-            const double mpp = L.M[m * RS + jj], mpq = L.M[m * RS + F + jj];
-            const double mqp = L.M[(F + m) * RS + jj], mqq = L.M[(F + m) * RS + F + jj];
-            const double sj = P->sqrt_gamma[jj], isj = P->inv_sqrt_gamma[jj];
-            are[jj] = 0.5 * (sgc * mqq * isj + mpp * sj * isgc);
-            aim[jj] = 0.5 * (-sgc * mqp * sj + mpq * isgc * isj);
+        // continuous branch: theta accumulates the principal argument of
+        // det(A_t) conj(det(A_{t-dt})) e^{i dt sum gamma}, which equals the step of
+        // arg(det(A) e^{i t sum gamma}) wrapped to (-pi, pi]; det(A) is rescaled by
+        // a power of two (argument unchanged) so the products cannot overflow.
+        if (c < F) {
+            int ex;
+            (void)frexp(fmax(fabs(dAr), fabs(dAi)), &ex);
+            dAr = ldexp(dAr, -ex);
+            dAi = ldexp(dAi, -ex);
+            const double ur = dAr * prev_r + dAi * prev_i;
+            const double ui = dAi * prev_r - dAr * prev_i;
+            const double zr = ur * P->cos_gdt - ui * P->sin_gdt;
+            const double zi = ur * P->sin_gdt + ui * P->cos_gdt;
+            theta += datan2(zi, zr, &P->mc);
+            prev_r = dAr;
+            prev_i = dAi;
+            phi = 0.5 * (theta - P->sum_gamma * t);
         }
-
-        double dAr, dAi;
-        lu_det_complex<F, F>(are, aim, m, c < F, L, dAr, dAi);
-        double sn, cs;
-        sincos(P->sum_gamma * t, &sn, &cs);
-        const double zr = dAr * cs - dAi * sn, zi = dAr * sn + dAi * cs;
-        const double r = atan2(zi, zr);
-        theta += wrap_pi(r - rprev);
-        rprev = r;
-        phi = 0.5 * (theta - P->sum_gamma * t);
         if (!isfinite(phi) || !isfinite(S)) good = false;
 
         if (live && c == 0) A.amp[(int64_t)stp * NP + jr] = amplitude(P);
@@ -375,7 +389,8 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(traj_wa
             }
             A.scal[SC_S * NP + jr] = S;
             A.scal[SC_THETA * NP + jr] = theta;
-            A.scal[SC_RPREV * NP + jr] = rprev;
+            A.scal[SC_PREV_RE * NP + jr] = prev_r;
+            A.scal[SC_PREV_IM * NP + jr] = prev_i;
             A.scal[SC_PHI * NP + jr] = phi;
             A.scal[SC_GOOD * NP + jr] = good ? 1.0 : 0.0;
             A.scal[SC_DETM * NP + jr] = detM;
