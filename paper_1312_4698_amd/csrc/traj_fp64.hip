@@ -1,29 +1,34 @@
 // FP64 trajectory kernel of the TA-SC-IVR spectrum for gfx950.
 //
-// One trajectory is owned by a group of G = 2F lanes of a wave64 (64/G
-// trajectories per wave).  During propagation lane c holds column c of the
-// 2F x 2F monodromy matrix M = d(p_t, q_t)/d(p_0, q_0), i.e. the tangent
-// vector (dp, dq) of one initial direction; every lane also holds the
-// trajectory's p and q, and lane c evaluates the potential terms of mode
-// c mod F.  After each step M is transposed through LDS so that lane r holds
-// row r, and det(M) (stability monitor after Eq. (5)) and det(A) (the
-// Herman-Kluk prefactor matrix of Eq. (5)) are taken by Gaussian elimination
-// with partial pivoting across the lanes of the group: the pivot is chosen by
-// an LDS max over packed (|a|, position) keys and broadcast through LDS.
+// One trajectory is owned by a group of F lanes of a wave64 (floor(64/F)
+// trajectories per wave).  Lane c owns degree of freedom c:
+//  * during the symplectic step it carries two columns of the 2F x 2F
+//    monodromy matrix M = d(p_t, q_t)/d(p_0, q_0): the tangent vectors of the
+//    initial directions p0_c and q0_c; it also carries the trajectory's p and
+//    q, and evaluates the Morse terms of mode c, which it shares with the
+//    group through LDS;
+//  * after each step M is transposed through LDS so that lane c holds rows c
+//    and F + c; from them it forms row c of the Herman-Kluk prefactor matrix A
+//    of Eq. (5) locally, and the group takes det(A) (complex, F x F, one row
+//    per lane) and det(M) (real, 2F x 2F, two rows per lane; the stability
+//    monitor after Eq. (5)) by Gaussian elimination with partial pivoting
+//    across its lanes: one LDS atomic max over packed (|a|, position) keys
+//    picks each pivot, the pivot lane publishes its row, the live rows read it
+//    back as a broadcast.
 //
 // The fourth-order symplectic step is the drift-kick-drift triple jump
-// (Yoshida / Forest-Ruth); each kick evaluates the gradient and the Hessian
+// (Yoshida / Forest-Ruth); each kick evaluates gradient, Hessian and potential
 // of V = sum_i [k_i q_i^2/2 + D_i (1 - e^{-a_i q_i})^2] + sum_{i<j} l_ij q_i^2 q_j^2
-// and applies the Hessian to the tangent column in factored form,
+// and applies the Hessian to each tangent column in factored form,
 //   H dq = h o dq + 4 q o (Lambda (q o dq)),  h_i = d^2V/dq_i^2,
-// with Lambda the symmetric zero-diagonal coupling matrix (kept in scalar
-// registers).  The action follows the discrete Lagrangian of the stages
-// (+h |p|^2/2 per drift, -h V per kick).  The prefactor phase is kept on a
-// continuous branch by unwrapping arg(det(A) e^{i t sum gamma}) step by step,
-// phi = (theta - t sum gamma)/2 (separable approximation after Eq. (9)).
-// Each step writes the amplitude <chi|p_t,q_t> e^{i (S_t + phi_t)} (zero once
-// the trajectory is flagged) into a time-major [t][trajectory] matrix, the
-// left operand of the Fourier GEMM.
+// with Lambda the symmetric zero-diagonal coupling matrix (scalar operands).
+// The action follows the discrete Lagrangian of the stages (+h |p|^2/2 per
+// drift, -h V per kick).  The prefactor phase is kept on a continuous branch
+// by accumulating the principal argument of det(A_t) conj(det(A_{t-dt}))
+// e^{i dt sum gamma}; phi = (theta - t sum gamma)/2 (the separable
+// approximation after Eq. (9)).  Each step writes the amplitude
+// <chi|p_t,q_t> e^{i (S_t + phi_t)} (zero once the trajectory is flagged) into
+// a time-major [t][trajectory] matrix, the left operand of the Fourier GEMM.
 #include <math.h>
 
 #include "scivr_internal.h"
@@ -34,10 +39,11 @@ namespace {
 template <int F>
 struct alignas(16) GroupLds {
     static constexpr int N2 = 2 * F;
-    static constexpr int RS = N2 + 2;  // row stride of the transposed matrix (keeps 16-byte rows)
-    double M[N2 * RS];                 // transposed monodromy matrix, row r at r * RS
+    static constexpr int RS = N2;      // row stride of the half-matrix transpose buffer
+    double T[F * RS];                  // one half (F rows) of the transposed monodromy matrix
     double pivM[N2];                   // pivot row of the real elimination
     double pivA[N2];                   // pivot row of the complex elimination (re, im interleaved)
+    double qv[F + (F & 1)], pv_mom[F + (F & 1)];  // the trajectory's q and p, one entry per owning lane
     double pg[F + (F & 1)], ph[F + (F & 1)], pv[F + (F & 1)];
     unsigned long long slotM[N2];      // per-step argmax keys of the two eliminations
     unsigned long long slotA[F + (F & 1)];
@@ -56,10 +62,10 @@ __device__ inline void lds_order()
 
 typedef const __attribute__((address_space(4))) ProblemDev *ConstProblem;
 
-// A fresh, opaque handle to the trajectory-independent constants.  Calling it
-// at the top of every step keeps their ~100 uniform doubles as scalar-cache
-// loads inside the loop instead of letting them be hoisted into (and spilled
-// out of) the scalar register file.
+// A fresh, opaque handle to the trajectory-independent constants.  Taking it
+// inside the time loop keeps their uniform doubles as scalar-cache loads there
+// instead of letting them be hoisted into (and spilled out of) the scalar
+// register file.
 __device__ inline ConstProblem opaque(const ProblemDev *P)
 {
     uint64_t v = (uint64_t)P;
@@ -67,59 +73,82 @@ __device__ inline ConstProblem opaque(const ProblemDev *P)
     return (ConstProblem)v;
 }
 
-// Gaussian elimination with partial pivoting across the lanes of a group.
-// Lane-local a[] is the row at position `pos` (lanes with alive == false hold
-// no row).  Each step takes the column maximum with one LDS atomic max over
-// packed (|a_k|, 63 - pos) keys (ties go to the lowest position, as in a
-// row-swapping LU); only the winning lane then publishes its row into the
-// pivot buffer, which the group reads back as a broadcast.  The row at
-// position k and the pivot swap positions; the sign of the determinant flips
-// when they differ.  Apart from the pivot's store, everything is branch-free.
-template <int N>
-__device__ inline double lu_det_real(double (&a)[N], int pos, bool alive, double *piv, unsigned long long *slot)
+__device__ inline unsigned long long pivot_key(double mag, int pos)
 {
-    if (alive) slot[pos] = 0ull;
+    return (dbits(mag) & ~63ull) | (unsigned long long)(63 - pos);
+}
+
+// det of the real N x N matrix (N = 2F) whose rows at positions pos0, pos1
+// live in lane-local a0[], a1[].  Each step: LDS atomic max over packed
+// (|a_k|, 63 - pos) keys of the live rows (ties go to the lowest position, as
+// in a row-swapping LU); the lane holding the winner publishes that row; live
+// rows read it back and eliminate.  The row at position k and the pivot swap
+// positions, and the determinant changes sign when they differ.
+template <int N>
+__device__ inline double lu_det_real2(double (&a0)[N], double (&a1)[N], int pos0, int pos1, double *piv,
+                                      unsigned long long *slot)
+{
+    bool alive0 = true, alive1 = true;
+    slot[pos0] = 0ull;
+    slot[pos1] = 0ull;
     double det = 1.0;
 #pragma unroll
     for (int k = 0; k < N; ++k) {
+        const unsigned long long k0 = alive0 ? pivot_key(fabs(a0[k]), pos0) : 0ull;
+        const unsigned long long k1 = alive1 ? pivot_key(fabs(a1[k]), pos1) : 0ull;
+        const unsigned long long kk = k0 > k1 ? k0 : k1;
         lds_order();
-        if (alive) atomicMax(&slot[k], (dbits(fabs(a[k])) & ~63ull) | (unsigned long long)(63 - pos));
+        if (kk) atomicMax(&slot[k], kk);
         lds_order();
         const unsigned long long win = __hip_atomic_load(&slot[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
         const int ppos = 63 - (int)(win & 63ull);
-        const bool isp = alive && pos == ppos;
-        if (isp) {
+        const bool isp0 = alive0 && pos0 == ppos;
+        const bool isp1 = alive1 && pos1 == ppos;
+        if (isp0) {
 #pragma unroll
-            for (int jj = k; jj < N; ++jj) piv[jj] = a[jj];
+            for (int jj = k; jj < N; ++jj) piv[jj] = a0[jj];
+        }
+        if (isp1) {
+#pragma unroll
+            for (int jj = k; jj < N; ++jj) piv[jj] = a1[jj];
         }
         lds_order();
         const double pk = piv[k];
         det *= (ppos != k) ? -pk : pk;
-        pos = (alive && pos == k) ? ppos : pos;
-        alive = alive && !isp;
-        if (alive) {  // rows already eliminated (and the pivot) skip the broadcast read
-            const double l = a[k] * rcp_nr(pk);
+        pos0 = (alive0 && pos0 == k) ? ppos : pos0;
+        pos1 = (alive1 && pos1 == k) ? ppos : pos1;
+        alive0 = alive0 && !isp0;
+        alive1 = alive1 && !isp1;
+        if (alive0 || alive1) {  // lanes whose rows are all eliminated skip the broadcast read
+            const double inv = rcp_nr(pk);
+            const double l0 = alive0 ? a0[k] * inv : 0.0;
+            const double l1 = alive1 ? a1[k] * inv : 0.0;
 #pragma unroll
-            for (int jj = k + 1; jj < N; ++jj) a[jj] = fma(-l, piv[jj], a[jj]);
+            for (int jj = k + 1; jj < N; ++jj) {
+                const double v = piv[jj];
+                a0[jj] = fma(-l0, v, a0[jj]);
+                a1[jj] = fma(-l1, v, a1[jj]);
+            }
         }
     }
     lds_order();
     return det;
 }
 
-// Complex version: rows (ar, ai); pivot on |a_k|^2; the pivot row is stored
-// interleaved (re, im).
+// det of the complex N x N matrix (N = F) whose row `pos` lives in (ar, ai);
+// pivot on |a_k|^2; the pivot row is published interleaved (re, im).
 template <int N>
-__device__ inline void lu_det_complex(double (&ar)[N], double (&ai)[N], int pos, bool alive, double *piv,
+__device__ inline void lu_det_complex(double (&ar)[N], double (&ai)[N], int pos, double *piv,
                                       unsigned long long *slot, double &dr, double &di)
 {
-    if (alive) slot[pos] = 0ull;
+    bool alive = true;
+    slot[pos] = 0ull;
     double zr = 1.0, zi = 0.0;
 #pragma unroll
     for (int k = 0; k < N; ++k) {
         const double m2 = fma(ar[k], ar[k], ai[k] * ai[k]);
         lds_order();
-        if (alive) atomicMax(&slot[k], (dbits(m2) & ~63ull) | (unsigned long long)(63 - pos));
+        if (alive) atomicMax(&slot[k], pivot_key(m2, pos));
         lds_order();
         const unsigned long long win = __hip_atomic_load(&slot[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
         const int ppos = 63 - (int)(win & 63ull);
@@ -156,54 +185,55 @@ __device__ inline void lu_det_complex(double (&ar)[N], double (&ai)[N], int pos,
     di = zi;
 }
 
-// Waves per SIMD the register allocator must allow (unified 512-register file):
-// small F keeps several waves resident to hide LDS and transcendental latency.
+// Waves per SIMD the register allocator must allow (unified 512-register file).
 template <int F>
-constexpr int traj_waves() { return F <= 2 ? 4 : (F <= 6 ? 3 : (F <= 12 ? 2 : 1)); }
+constexpr int traj_waves() { return F <= 3 ? 4 : (F <= 6 ? 3 : (F <= 12 ? 2 : 1)); }
 
 template <int F>
-__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(traj_waves<F>(), 8))) traj_fp64_kernel(TrajArgs A, const ProblemDev *__restrict__ P0)
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(traj_waves<F>(), 8)))
+traj_fp64_kernel(TrajArgs A, const ProblemDev *__restrict__ P0)
 {
-    constexpr int G = 2 * F;
-    constexpr int TPW = 64 / G;
+    constexpr int N2 = 2 * F;
+    constexpr int TPW = 64 / F;
     constexpr int RS = GroupLds<F>::RS;
     __shared__ GroupLds<F> lds_all[TPW];
+    __shared__ double lam_lds[F * F];  // coupling matrix, shared by the wave's groups
 
     const int lane = threadIdx.x;
-    const int grp = lane / G;
-    // Lanes beyond the last full group own no trajectory.  They leave at once;
-    // nothing below synchronises the workgroup, so the rest of the wave runs on
-    // with them masked off.
+    const ProblemDev *__restrict__ P = P0;
+    for (int idx = lane; idx < F * F; idx += 64) lam_lds[idx] = P->lam[(idx / F) * FMAX + idx % F];
+    const int grp = lane / F;
+    // Lanes beyond the last full group own no trajectory.  They leave once the
+    // shared table is written; nothing below synchronises the workgroup, so the
+    // rest of the wave runs on with them masked off.
     if (grp >= TPW) return;
-    const int c = lane - grp * G;
-    const int m = (c < F) ? c : c - F;
+    const int c = lane - grp * F;  // degree of freedom owned by this lane
     GroupLds<F> &L = lds_all[grp];
     const int64_t j = (int64_t)blockIdx.x * TPW + grp;
     const bool live = j < A.n;
     const int64_t jr = live ? j : 0;
     const int64_t NP = A.npad;
 
-    const ProblemDev *__restrict__ P = P0;
-    // constants of the lane's own mode m
-    const double km = P->k[m], Dm = P->D[m], am = P->a[m];
-    const double sgc = P->sqrt_gamma[m], isgc = P->inv_sqrt_gamma[m];
-    double lamrow[F];
-#pragma unroll
-    for (int i = 0; i < F; ++i) lamrow[i] = P->lam[m * FMAX + i];
+    // constants of the lane's own mode c
+    const double kc = P->k[c], Dc = P->D[c], ac = P->a[c];
+    const double sgc = P->sqrt_gamma[c], isgc = P->inv_sqrt_gamma[c];
 
-    double p[F], q[F], dp[F], dq[F];
-    double pm, qm, S, theta, prev_r, prev_i, phi, detM, maxdev;
+    // pc, qc: the trajectory's momentum and position of mode c (the group's
+    // full p and q live in LDS); columns c ("P": d/dp0_c) and F + c ("Q":
+    // d/dq0_c) of M, split into their p and q halves.
+    double dpP[F], dqP[F], dpQ[F], dqQ[F];
+    double pc, qc, S, theta, prev_r, prev_i, phi, detM, maxdev;
     bool good;
     if (A.step_begin == 0) {
 #pragma unroll
         for (int i = 0; i < F; ++i) {
-            p[i] = A.p0[i * NP + jr];
-            q[i] = A.q0[i * NP + jr];
-            dp[i] = (i == c) ? 1.0 : 0.0;
-            dq[i] = (F + i == c) ? 1.0 : 0.0;
+            dpP[i] = (i == c) ? 1.0 : 0.0;
+            dqP[i] = 0.0;
+            dpQ[i] = 0.0;
+            dqQ[i] = (i == c) ? 1.0 : 0.0;
         }
-        pm = A.p0[m * NP + jr];
-        qm = A.q0[m * NP + jr];
+        pc = A.p0[c * NP + jr];
+        qc = A.q0[c * NP + jr];
         S = theta = phi = prev_i = 0.0;
         prev_r = 1.0;  // det(A) = 1 at t = 0
         detM = 1.0;
@@ -212,13 +242,13 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(traj_wa
     } else {
 #pragma unroll
         for (int i = 0; i < F; ++i) {
-            p[i] = A.p[i * NP + jr];
-            q[i] = A.q[i * NP + jr];
-            dp[i] = A.Mst[(int64_t)(i * G + c) * NP + jr];
-            dq[i] = A.Mst[(int64_t)((F + i) * G + c) * NP + jr];
+            dpP[i] = A.Mst[(int64_t)(i * N2 + c) * NP + jr];
+            dqP[i] = A.Mst[(int64_t)((F + i) * N2 + c) * NP + jr];
+            dpQ[i] = A.Mst[(int64_t)(i * N2 + F + c) * NP + jr];
+            dqQ[i] = A.Mst[(int64_t)((F + i) * N2 + F + c) * NP + jr];
         }
-        pm = A.p[m * NP + jr];
-        qm = A.q[m * NP + jr];
+        pc = A.p[c * NP + jr];
+        qc = A.q[c * NP + jr];
         S = A.scal[SC_S * NP + jr];
         theta = A.scal[SC_THETA * NP + jr];
         prev_r = A.scal[SC_PREV_RE * NP + jr];
@@ -228,16 +258,20 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(traj_wa
         detM = A.scal[SC_DETM * NP + jr];
         maxdev = A.scal[SC_MAXDEV * NP + jr];
     }
+    L.qv[c] = qc;
+    L.pv_mom[c] = pc;
+    lds_order();
 
-    // amplitude <chi|p,q> e^{i(S + phi)} of the current state (zero when bad)
+    // amplitude <chi|p,q> e^{i(S + phi)} of the published state (zero when bad)
     auto amplitude = [&](auto PP) -> double2 {
         double ex = 0.0, ph = 0.0;
 #pragma unroll
         for (int i = 0; i < F; ++i) {
-            const double dqe = PP->q_eq[i] - q[i];
-            const double dpe = PP->p_eq[i] - p[i];
+            const double qi = L.qv[i], pi = L.pv_mom[i];
+            const double dqe = PP->q_eq[i] - qi;
+            const double dpe = PP->p_eq[i] - pi;
             ex += -0.25 * PP->gamma[i] * dqe * dqe - dpe * dpe * PP->inv4gamma[i];
-            ph += 0.5 * dqe * (PP->p_eq[i] + p[i]);
+            ph += 0.5 * dqe * (PP->p_eq[i] + pi);
         }
         double s, co;
         dsincos(ph + S + phi, &PP->mc, &s, &co);
@@ -251,142 +285,154 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(traj_wa
     if (A.step_begin == 0 && live && c == 0) A.amp[jr] = amplitude(P);
 
     for (int step = A.step_begin; step < A.step_end; ++step) {
-        ConstProblem P = opaque(P0);
+        ConstProblem Ps = opaque(P0);
 #pragma unroll 1
         for (int s = 0; s < 4; ++s) {
+            ConstProblem Pk = opaque(P0);
             // ---- drift ----
-            const double h = P->hd[s];
-            double kin = 0.0;
+            const double h = Pk->hd[s];
+            if (c == 0) {  // the action is carried by lane 0 only
+                double kin = 0.0;
 #pragma unroll
-            for (int i = 0; i < F; ++i) kin += 0.5 * p[i] * p[i];
+                for (int i = 0; i < F; ++i) {
+                    const double pi = L.pv_mom[i];
+                    kin += 0.5 * pi * pi;
+                }
+                S = fma(h, kin, S);
+            }
+            qc = fma(h, pc, qc);
 #pragma unroll
             for (int i = 0; i < F; ++i) {
-                q[i] = fma(h, p[i], q[i]);
-                dq[i] = fma(h, dp[i], dq[i]);
-            }
-            qm = fma(h, pm, qm);
-            S = fma(h, kin, S);
-            if (s == 3) break;
-            // ---- kick ----
-            ConstProblem Pk = opaque(P0);
-            const double hk = Pk->hc[s];
-            double q2[F];
-#pragma unroll
-            for (int i = 0; i < F; ++i) q2[i] = q[i] * q[i];
-            double sm = 0.0;
-#pragma unroll
-            for (int i = 0; i < F; ++i) sm = fma(lamrow[i], q2[i], sm);
-            const double e = dexp(-am * qm, &Pk->mc);
-            const double one_e = 1.0 - e;
-            const double gm = km * qm + 2.0 * Dm * am * e * one_e + 2.0 * qm * sm;
-            const double hm = km + 2.0 * Dm * am * am * e * (2.0 * e - 1.0) + 2.0 * sm;
-            const double vm = 0.5 * km * qm * qm + Dm * one_e * one_e + 0.5 * qm * qm * sm;
-            if (c < F) {
-                L.pg[c] = gm;
-                L.ph[c] = hm;
-                L.pv[c] = vm;
+                dqP[i] = fma(h, dpP[i], dqP[i]);
+                dqQ[i] = fma(h, dpQ[i], dqQ[i]);
             }
             lds_order();
-            double V = 0.0;
+            L.qv[c] = qc;
+            lds_order();
+            if (s == 3) break;
+            // ---- kick: mode c's terms, shared through LDS ----
+            const double hk = Pk->hc[s];
+            double q[F];
 #pragma unroll
-            for (int i = 0; i < F; ++i) {
-                p[i] = fma(-hk, L.pg[i], p[i]);
-                V += L.pv[i];
+            for (int i = 0; i < F; ++i) q[i] = L.qv[i];
+            double sm = 0.0;
+#pragma unroll
+            for (int i = 0; i < F; ++i) sm = fma(lam_lds[c * F + i], q[i] * q[i], sm);
+            const double e = dexp(-ac * qc, &Pk->mc);
+            const double one_e = 1.0 - e;
+            const double gc = kc * qc + 2.0 * Dc * ac * e * one_e + 2.0 * qc * sm;
+            const double hc = kc + 2.0 * Dc * ac * ac * e * (2.0 * e - 1.0) + 2.0 * sm;
+            const double vc = 0.5 * kc * qc * qc + Dc * one_e * one_e + 0.5 * qc * qc * sm;
+            pc = fma(-hk, gc, pc);
+            L.ph[c] = hc;
+            L.pv[c] = vc;
+            L.pv_mom[c] = pc;
+            lds_order();
+            if (c == 0) {
+                double V = 0.0;
+#pragma unroll
+                for (int i = 0; i < F; ++i) V += L.pv[i];
+                S = fma(-hk, V, S);
             }
-            pm = fma(-hk, gm, pm);
-            S = fma(-hk, V, S);
-            // tangent kick: dp -= hk (h o dq + 4 q o Lambda (q o dq))
-            double u[F], w[F];
+            // tangent kick, one column after the other: dp -= hk (h o dq + 4 q o Lambda (q o dq))
 #pragma unroll
-            for (int i = 0; i < F; ++i) {
-                u[i] = q[i] * dq[i];
-                w[i] = 0.0;
-            }
+            for (int col = 0; col < 2; ++col) {
+                double(&dp)[F] = col ? dpQ : dpP;
+                double(&dq)[F] = col ? dqQ : dqP;
+                double u[F], w[F];
 #pragma unroll
-            for (int i = 0; i < F; ++i)
-#pragma unroll
-                for (int jj = i + 1; jj < F; ++jj) {
-                    const double l = P->lam[i * FMAX + jj];
-                    w[i] = fma(l, u[jj], w[i]);
-                    w[jj] = fma(l, u[i], w[jj]);
+                for (int i = 0; i < F; ++i) {
+                    u[i] = q[i] * dq[i];
+                    w[i] = 0.0;
                 }
 #pragma unroll
-            for (int i = 0; i < F; ++i) dp[i] = fma(-hk, fma(L.ph[i], dq[i], 4.0 * q[i] * w[i]), dp[i]);
+                for (int i = 0; i < F; ++i)
+#pragma unroll
+                    for (int jj = i + 1; jj < F; ++jj) {
+                        const double l = Pk->lam[i * FMAX + jj];
+                        w[i] = fma(l, u[jj], w[i]);
+                        w[jj] = fma(l, u[i], w[jj]);
+                    }
+#pragma unroll
+                for (int i = 0; i < F; ++i) dp[i] = fma(-hk, fma(L.ph[i], dq[i], 4.0 * q[i] * w[i]), dp[i]);
+            }
             lds_order();
         }
 
         const int stp = step + 1;
-        const double t = (double)stp * P->dt;
+        const double t = (double)stp * Ps->dt;
 
-        // ---- transpose M through LDS: column c -> rows ----
+        // ---- transpose M through LDS in two halves: lane c ends with rows c and F + c ----
+        double r0[N2], r1[N2];  // rows c (p_c) and F + c (q_c)
 #pragma unroll
         for (int i = 0; i < F; ++i) {
-            L.M[i * RS + c] = dp[i];
-            L.M[(F + i) * RS + c] = dq[i];
+            L.T[i * RS + c] = dpP[i];
+            L.T[i * RS + F + c] = dpQ[i];
         }
         lds_order();
+#pragma unroll
+        for (int jj = 0; jj < N2; ++jj) r0[jj] = L.T[c * RS + jj];
+        lds_order();
+#pragma unroll
+        for (int i = 0; i < F; ++i) {
+            L.T[i * RS + c] = dqP[i];
+            L.T[i * RS + F + c] = dqQ[i];
+        }
+        lds_order();
+#pragma unroll
+        for (int jj = 0; jj < N2; ++jj) r1[jj] = L.T[c * RS + jj];
+        lds_order();
 
-        // prefactor matrix row c: A[c][jj] from M rows c and F+c, then det(A);
-        // only lanes c < F take part (they alone carry the phase, lane 0 writes
-        // the amplitude), the upper half of the group is masked off meanwhile
-        double dAr = 0.0, dAi = 0.0;
-        if (c < F) {
+        // prefactor matrix row c from rows c (Mpp, Mpq) and F + c (Mqp, Mqq), then det(A)
+        double dAr, dAi;
+        {
             double are[F], aim[F];
 #pragma unroll
             for (int jj = 0; jj < F; ++jj) {
-                const double mpp = L.M[c * RS + jj], mpq = L.M[c * RS + F + jj];
-                const double mqp = L.M[(F + c) * RS + jj], mqq = L.M[(F + c) * RS + F + jj];
-                const double sj = P->sqrt_gamma[jj], isj = P->inv_sqrt_gamma[jj];
-                are[jj] = 0.5 * (sgc * mqq * isj + mpp * sj * isgc);
-                aim[jj] = 0.5 * (-sgc * mqp * sj + mpq * isgc * isj);
+                const double sj = Ps->sqrt_gamma[jj], isj = Ps->inv_sqrt_gamma[jj];
+                are[jj] = 0.5 * (sgc * r1[F + jj] * isj + r0[jj] * sj * isgc);
+                aim[jj] = 0.5 * (-sgc * r1[jj] * sj + r0[F + jj] * isgc * isj);
             }
-            lu_det_complex<F>(are, aim, c, true, L.pivA, L.slotA, dAr, dAi);
+            lu_det_complex<F>(are, aim, c, L.pivA, L.slotA, dAr, dAi);
         }
 
         // stability monitor |det(M)^2 - 1| on checked steps
         const bool checked = (A.check_every <= 1) || (stp % A.check_every == 0) || (stp == A.n_steps);
         if (checked) {
-            double row[G];
-#pragma unroll
-            for (int jj = 0; jj < G; ++jj) row[jj] = L.M[c * RS + jj];
-            const double dM = lu_det_real<G>(row, c, true, L.pivM, L.slotM);
+            const double dM = lu_det_real2<N2>(r0, r1, c, F + c, L.pivM, L.slotM);
             const double dev = fabs(dM * dM - 1.0);
             detM = dM;
             if (!(dev <= maxdev)) maxdev = dev;
-            if (!(dev <= P->det_tol)) good = false;
+            if (!(dev <= Ps->det_tol)) good = false;
         }
 
         // continuous branch: theta accumulates the principal argument of
         // det(A_t) conj(det(A_{t-dt})) e^{i dt sum gamma}, which equals the step of
         // arg(det(A) e^{i t sum gamma}) wrapped to (-pi, pi]; det(A) is rescaled by
         // a power of two (argument unchanged) so the products cannot overflow.
-        if (c < F) {
+        if (c == 0) {
             int ex;
             (void)frexp(fmax(fabs(dAr), fabs(dAi)), &ex);
             dAr = ldexp(dAr, -ex);
             dAi = ldexp(dAi, -ex);
             const double ur = dAr * prev_r + dAi * prev_i;
             const double ui = dAi * prev_r - dAr * prev_i;
-            const double zr = ur * P->cos_gdt - ui * P->sin_gdt;
-            const double zi = ur * P->sin_gdt + ui * P->cos_gdt;
-            theta += datan2(zi, zr, &P->mc);
+            const double zr = ur * Ps->cos_gdt - ui * Ps->sin_gdt;
+            const double zi = ur * Ps->sin_gdt + ui * Ps->cos_gdt;
+            theta += datan2(zi, zr, &Ps->mc);
             prev_r = dAr;
             prev_i = dAi;
-            phi = 0.5 * (theta - P->sum_gamma * t);
+            phi = 0.5 * (theta - Ps->sum_gamma * t);
+            if (!isfinite(phi) || !isfinite(S)) good = false;
+            if (live) A.amp[(int64_t)stp * NP + jr] = amplitude(Ps);
         }
-        if (!isfinite(phi) || !isfinite(S)) good = false;
-
-        if (live && c == 0) A.amp[(int64_t)stp * NP + jr] = amplitude(P);
     }
 
     // ---- save the state for a later continuation and for inspection ----
     if (live) {
+        A.p[c * NP + jr] = pc;
+        A.q[c * NP + jr] = qc;
         if (c == 0) {
-#pragma unroll
-            for (int i = 0; i < F; ++i) {
-                A.p[i * NP + jr] = p[i];
-                A.q[i * NP + jr] = q[i];
-            }
             A.scal[SC_S * NP + jr] = S;
             A.scal[SC_THETA * NP + jr] = theta;
             A.scal[SC_PREV_RE * NP + jr] = prev_r;
@@ -398,8 +444,10 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(traj_wa
         }
 #pragma unroll
         for (int i = 0; i < F; ++i) {
-            A.Mst[(int64_t)(i * G + c) * NP + jr] = dp[i];
-            A.Mst[(int64_t)((F + i) * G + c) * NP + jr] = dq[i];
+            A.Mst[(int64_t)(i * N2 + c) * NP + jr] = dpP[i];
+            A.Mst[(int64_t)((F + i) * N2 + c) * NP + jr] = dqP[i];
+            A.Mst[(int64_t)(i * N2 + F + c) * NP + jr] = dpQ[i];
+            A.Mst[(int64_t)((F + i) * N2 + F + c) * NP + jr] = dqQ[i];
         }
     }
 }
@@ -407,7 +455,7 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(traj_wa
 template <int F>
 hipError_t launch_F(const TrajArgs &a, hipStream_t s)
 {
-    constexpr int TPW = 64 / (2 * F);
+    constexpr int TPW = 64 / F;
     const int64_t blocks = (a.n + TPW - 1) / TPW;
     if (blocks <= 0) return hipSuccess;
     hipLaunchKernelGGL(traj_fp64_kernel<F>, dim3((unsigned)blocks), dim3(64), 0, s, a, a.prob);
