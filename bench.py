@@ -33,6 +33,7 @@ sys.path.insert(0, ROOT)
 
 FP64_VALU_PEAK_TFLOPS = 78.6   # MI355X FP64 vector: 256 CU x 2.4 GHz x 128 flop/clk
 FP64_MFMA_PEAK_TFLOPS = 78.6   # MI355X FP64 matrix (dense)
+F16_MFMA_PEAK_TFLOPS = 2500.0  # MI355X FP16 matrix (dense)
 HBM_PEAK_GBS = 8000.0
 
 
@@ -69,7 +70,7 @@ def _source_hash(*names):
 def _profile_traffic(kernel_prefix: str, src_hash: str):
     """HBM bytes per launch from a committed rocprofv3 counter summary, if it
     was taken on the current kernel source; else None."""
-    path = os.path.join(ROOT, "profiles", "traj_fp64_F9_N262144_counters.txt")
+    path = os.path.join(ROOT, "profiles", f"traj_{kernel_prefix}_counters.txt")
     if not os.path.exists(path):
         return None
     txt = open(path).read()
@@ -94,14 +95,46 @@ def cpu_baseline(prob, n_sample: int, seed: int):
                       f"{prob.n_energies} energies), {dt:.1f} s wall"}
 
 
+def run_form(scivr, torch, prob, n, steps, warmup, seed0=1000):
+    """Time `steps` whole passes (sample + propagate + accumulate) of one form."""
+    stream = torch.cuda.current_stream()
+    ctx = scivr.Context(prob, max_traj=n)
+
+    def one_step(i):
+        ctx.sample_husimi(seed=seed0 + i, n_traj=n, stream=stream)
+        ctx.propagate(0, prob.n_steps, stream=stream)
+        ctx.accumulate(stream=stream)
+
+    for i in range(warmup):
+        one_step(i)
+        print(f"[bench] {prob.name} warmup {i} done", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    ctx.reset_spectrum(stream=stream)
+    ctx.timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        one_step(warmup + i)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kt = ctx.kernel_times()
+    I, n_good, n_total = ctx.read_spectrum()
+    ctx.close()
+    print(f"[bench] {prob.name}: {steps} steps in {wall:.3f} s; kernels {kt}", file=sys.stderr, flush=True)
+    return {"wall": wall, "kt": kt, "I": I, "n_good": n_good, "n_total": n_total}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="F9_fp64")
+    ap.add_argument("--workload", default="F9_mixed")
+    ap.add_argument("--plain", default="F9_fp64", help="plain FP64 form timed alongside ('' to skip)")
     ap.add_argument("--n-traj", type=int, default=0, help="override the trajectory count")
     ap.add_argument("--cpu-sample", type=int, default=512, help="oracle trajectories for the CPU baseline (0: skip)")
+    ap.add_argument("--copy-calibration", type=int, default=0,
+                    help="only copy this many bytes device-to-device (counter calibration) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; the path shards by trajectory index "
@@ -109,40 +142,32 @@ def main():
         sys.exit(2)
 
     import torch
-    from paper_1312_4698_amd import inputs, scivr
+    from paper_1312_4698_amd import inputs, peaks, scivr
 
     if not torch.cuda.is_available():
         print(json.dumps({"error": "no GPU visible"}))
         sys.exit(1)
+    if args.copy_calibration:
+        a = torch.ones(args.copy_calibration // 8, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copied_bytes": a.numel() * 8}))
+        return
     prob, n = inputs.workload(args.workload)
     if args.n_traj:
         n = args.n_traj
-    stream = torch.cuda.current_stream()
-    ctx = scivr.Context(prob, max_traj=n)
     print(f"[bench] {args.workload}: F={prob.F} n={n} steps={prob.n_steps} K={prob.n_energies}", file=sys.stderr,
           flush=True)
+    main_run = run_form(scivr, torch, prob, n, args.steps, args.warmup)
+    plain = None
+    if args.plain:
+        pprob, _ = inputs.workload(args.plain)
+        plain = run_form(scivr, torch, pprob, n, args.steps, args.warmup)
 
-    def one_step(i):
-        ctx.sample_husimi(seed=1000 + i, n_traj=n, stream=stream)
-        ctx.propagate(0, prob.n_steps, stream=stream)
-        ctx.accumulate(stream=stream)
-
-    for i in range(args.warmup):
-        one_step(i)
-        print(f"[bench] warmup {i} done", file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    ctx.reset_spectrum(stream=stream)
-    ctx.timing(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        one_step(args.warmup + i)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    kt = ctx.kernel_times()
-    I, n_good, n_total = ctx.read_spectrum()
-    print(f"[bench] timed {args.steps} steps in {wall:.3f} s; kernels {kt}", file=sys.stderr, flush=True)
-
+    wall = main_run["wall"]
+    kt = main_run["kt"]
     ms_step = wall / args.steps * 1e3
     traj_steps = n * prob.n_steps
     value = traj_steps / (wall / args.steps)
@@ -151,10 +176,11 @@ def main():
     t_launch = ms_tr / max(n_tr, 1) / 1e3
     fl_launch = traj_flops_per_step(prob.F) * traj_steps
     achieved = fl_launch / t_launch / 1e12
-    src_hash = _source_hash("traj_fp64.hip")
-    traffic = _profile_traffic("traj_fp64", src_hash)
+    src_hash = _source_hash("traj.hip")
+    traffic = _profile_traffic(prob.name, src_hash)
     fo_launch = ms_fo / max(n_fo, 1) / 1e3
     fo_fl = fourier_flops(n, prob.n_steps + 1, prob.n_energies)
+    mixed = prob.precision == inputs.PRECISION_MIXED
 
     out = {
         "metric": "trajectory-steps/s at F=9",
@@ -167,17 +193,17 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f32+f64 trajectory, f16x2 MFMA Fourier" if mixed else "f64",
         "data": "synthetic",
         "config": {
             "workload": f"{args.workload}: Morse + quartic coupling, F={prob.F}, {n} Husimi trajectories, "
                         f"{prob.n_steps} steps of dt={prob.dt} au, {prob.n_energies} energies on "
                         f"[{prob.e_min}, {prob.e_max}] hartree",
             "F": prob.F, "n_traj": n, "n_steps": prob.n_steps, "n_energies": prob.n_energies,
-            "precision": "fp64", "parallelism": "single GPU",
+            "precision": "mixed" if mixed else "fp64", "parallelism": "single GPU",
         },
         "roofline": {
-            "kernel": "traj_fp64_kernel",
+            "kernel": "traj_kernel",
             "bound": "alu",
             "achieved": achieved,
             "peak": FP64_VALU_PEAK_TFLOPS,
@@ -188,22 +214,38 @@ def main():
             "flops_per_launch": fl_launch,
             "source_hash": src_hash,
         },
-        "roofline_fourier": {
-            "kernel": "fourier_fp64_kernel",
+        "fourier": {
+            "kernel": "fourier_f16_kernel" if mixed else "fourier_fp64_kernel",
             "bound": "mfma",
-            "achieved": fo_fl / fo_launch / 1e12,
-            "peak": FP64_MFMA_PEAK_TFLOPS,
-            "unit": "TFLOP/s",
-            "frac": fo_fl / fo_launch / 1e12 / FP64_MFMA_PEAK_TFLOPS,
+            "achieved_useful_TFLOPs": fo_fl / fo_launch / 1e12,
+            "peak_TFLOPs": F16_MFMA_PEAK_TFLOPS / 3.0 if mixed else FP64_MFMA_PEAK_TFLOPS,
             "launch_ms": fo_launch * 1e3,
         },
-        "n_good_fraction": n_good / max(n_total, 1),
+        "n_good_fraction": main_run["n_good"] / max(main_run["n_total"], 1),
         "cpu_baseline": None,
     }
+    if mixed:
+        out["fourier"]["note"] = ("three FP16 products per real product (hi*hi + hi*lo + lo*hi): the useful "
+                                  "peak is the dense FP16 MFMA peak / 3")
+    if plain is not None:
+        pv = traj_steps / (plain["wall"] / args.steps)
+        E = prob.energies()
+        T = prob.total_time
+        pr = peaks.find_peaks(E, plain["I"], T)
+        pt = peaks.find_peaks(E, main_run["I"], T)
+        worst, missing = peaks.peak_errors(pr, pt, tol=20.0 / inputs.CM1_PER_HARTREE)
+        out["plain_fp64"] = {
+            "value": pv, "ms_per_step": plain["wall"] / args.steps * 1e3,
+            "trajectory_ms": plain["kt"]["trajectory"][1] / max(plain["kt"]["trajectory"][0], 1),
+            "fourier_ms": plain["kt"]["fourier"][1] / max(plain["kt"]["fourier"][0], 1),
+            "speedup_of_value": value / pv,
+            "peak_error_cm1": worst * inputs.CM1_PER_HARTREE, "peaks_compared": len(pr), "peaks_missing": missing,
+            "same_samples": True,
+        }
     if args.cpu_sample > 0:
         print(f"[bench] cpu baseline: oracle on {args.cpu_sample} trajectories", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(prob, args.cpu_sample, seed=77)
-    ctx.close()
+        pprob = prob.replace(precision=inputs.PRECISION_FP64)
+        out["cpu_baseline"] = cpu_baseline(pprob, args.cpu_sample, seed=77)
     print(json.dumps(out))
 
 

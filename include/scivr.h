@@ -55,7 +55,7 @@ typedef int32_t scivr_status;
 #define SCIVR_EUNSUPPORTED (-6) /* valid request this build does not implement */
 
 #define SCIVR_PRECISION_FP64 0  /* every step in FP64 */
-#define SCIVR_PRECISION_MIXED 1 /* FP32 trajectory, FP64 monodromy/prefactor, split-BF16 Fourier GEMM */
+#define SCIVR_PRECISION_MIXED 1 /* FP32 trajectory and Kahan action, FP64 monodromy/prefactor/branch, split-FP16 Fourier GEMM */
 
 #define SCIVR_MEM_HOST 0
 #define SCIVR_MEM_DEVICE 1
@@ -92,12 +92,14 @@ int32_t scivr_abi_version(void);
 /*
  * Validate the problem, select `device`, copy the parameters and allocate
  * every device buffer of a batch of max_traj trajectories (initial
- * conditions, state, the [n_steps+1][max_traj] complex amplitude matrix, the
- * time x energy phase table, spectrum accumulators).
+ * conditions, state, the amplitude matrix of n_steps+1 samples per
+ * trajectory, spectrum accumulators; FP64: complex [n_steps+1][max_traj] and
+ * the time x energy phase table; MIXED: four FP16 planes hi/lo of re/im in
+ * the time-blocked layout [t/8][max_traj][t%8]).
  * Errors: SCIVR_EINVAL (F out of range, n_steps < 1, n_energies < 2,
  * e_max <= e_min, gamma_i <= 0, dt <= 0, check_every < 1, max_traj < 1, a
- * non-finite parameter, NULL pointer), SCIVR_EUNSUPPORTED (precision not
- * built for this F), SCIVR_ENOMEM, SCIVR_EDEVICE.  On error *out is NULL and
+ * non-finite parameter, NULL pointer, precision not FP64/MIXED),
+ * SCIVR_ENOMEM, SCIVR_EDEVICE.  On error *out is NULL and
  * nothing is leaked.
  */
 scivr_status scivr_create(const scivr_problem *p, int32_t device, scivr_ctx **out);

@@ -22,7 +22,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libscivr.so")
 ARCH = os.environ.get("SCIVR_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["api.hip", "traj_fp64.hip", "fourier_fp64.hip", "aux_kernels.hip"]
+SOURCES = ["api.hip", "traj.hip", "fourier_fp64.hip", "fourier_f16.hip", "aux_kernels.hip"]
 
 HIPCC = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
 

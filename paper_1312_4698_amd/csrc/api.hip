@@ -33,7 +33,9 @@ struct scivr_ctx {
     ProblemDev *d_prob = nullptr;
     double *d_p0 = nullptr, *d_q0 = nullptr, *d_logrho = nullptr;
     double *d_p = nullptr, *d_q = nullptr, *d_scal = nullptr, *d_M = nullptr;
-    double2 *d_amp = nullptr, *d_phase = nullptr;
+    double2 *d_amp = nullptr, *d_phase = nullptr;  // FP64 form
+    _Float16 *d_amp16 = nullptr;                    // mixed form: 4 planes [nt16 / 8][npad][8]
+    int32_t nt16 = 0;                               // time samples per plane (multiple of 32)
     double *d_weight = nullptr, *d_part_spec = nullptr, *d_part_contrib = nullptr, *d_contrib = nullptr;
     double *d_total = nullptr;
     unsigned long long *d_ngood = nullptr;
@@ -100,8 +102,9 @@ hipError_t dalloc(T **p, size_t count)
 
 void free_all(scivr_ctx *c)
 {
-    void *ptrs[] = {c->d_prob, c->d_p0, c->d_q0, c->d_logrho, c->d_p, c->d_q, c->d_scal, c->d_M, c->d_amp,
-                    c->d_phase, c->d_weight, c->d_part_spec, c->d_part_contrib, c->d_contrib, c->d_total, c->d_ngood};
+    void *ptrs[] = {c->d_prob,   c->d_p0,        c->d_q0,           c->d_logrho,  c->d_p,     c->d_q,
+                    c->d_scal,   c->d_M,         c->d_amp,          c->d_amp16,   c->d_phase, c->d_weight,
+                    c->d_part_spec, c->d_part_contrib, c->d_contrib, c->d_total, c->d_ngood};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     for (auto &e : c->events) {
@@ -209,7 +212,6 @@ scivr_status scivr_create(const scivr_problem *p, int32_t device, scivr_ctx **ou
     for (int i = 0; i < F; ++i)
         if (!(p->gamma[i] > 0)) return SCIVR_EINVAL;
     if (p->precision != SCIVR_PRECISION_FP64 && p->precision != SCIVR_PRECISION_MIXED) return SCIVR_EINVAL;
-    if (p->precision != SCIVR_PRECISION_FP64) return SCIVR_EUNSUPPORTED;
     if ((int64_t)p->n_steps + 1 > (int64_t)INT32_MAX - 64 || p->n_energies > (1 << 24) || p->max_traj > (1ll << 31))
         return SCIVR_EINVAL;
 
@@ -231,6 +233,7 @@ scivr_status scivr_create(const scivr_problem *p, int32_t device, scivr_ctx **ou
     c->nt_pad = (int32_t)round_up(c->nt, GEMM_BK);
     c->nt_alloc = c->nt_pad + GEMM_BK;
     c->kpad = (int32_t)round_up(p->n_energies, GEMM_BN);
+    c->nt16 = (int32_t)round_up(c->nt, GEMM16_BK);
     c->row_tiles = (int32_t)(c->npad / GEMM_BM);
     c->col_tiles = c->kpad / GEMM_BN;
 
@@ -292,8 +295,13 @@ scivr_status scivr_create(const scivr_problem *p, int32_t device, scivr_ctx **ou
     A(dalloc(&c->d_q, F * NP));
     A(dalloc(&c->d_scal, NSCAL * NP));
     A(dalloc(&c->d_M, G2 * NP));
-    A(dalloc(&c->d_amp, (int64_t)c->nt_alloc * NP));
-    A(dalloc(&c->d_phase, (int64_t)c->nt_alloc * c->kpad));
+    const bool mixed = c->precision == SCIVR_PRECISION_MIXED;
+    if (mixed) {
+        A(dalloc(&c->d_amp16, 4ll * c->nt16 * NP));
+    } else {
+        A(dalloc(&c->d_amp, (int64_t)c->nt_alloc * NP));
+        A(dalloc(&c->d_phase, (int64_t)c->nt_alloc * c->kpad));
+    }
     A(dalloc(&c->d_weight, NP));
     A(dalloc(&c->d_part_spec, (int64_t)c->row_tiles * c->kpad));
     A(dalloc(&c->d_part_contrib, (int64_t)(c->kpad / 64) * NP));
@@ -309,12 +317,13 @@ scivr_status scivr_create(const scivr_problem *p, int32_t device, scivr_ctx **ou
     }
     hipStream_t s0 = nullptr;
     e = hipMemcpy(c->d_prob, &h, sizeof h, hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = launch_fill_zero((double *)c->d_amp, 2ll * c->nt_alloc * NP, s0);
+    if (e == hipSuccess && !mixed) e = launch_fill_zero((double *)c->d_amp, 2ll * c->nt_alloc * NP, s0);
+    if (e == hipSuccess && mixed) e = launch_fill_zero((double *)c->d_amp16, (int64_t)c->nt16 * NP, s0);
     if (e == hipSuccess) e = launch_fill_zero(c->d_logrho, NP, s0);
     if (e == hipSuccess) e = launch_fill_zero(c->d_scal, NSCAL * NP, s0);
     if (e == hipSuccess) e = launch_fill_zero(c->d_total, c->n_energies, s0);
     if (e == hipSuccess) e = launch_fill_zero((double *)c->d_ngood, 1, s0);
-    if (e == hipSuccess)
+    if (e == hipSuccess && !mixed)
         e = launch_phase_table(p->e_min, p->e_max, p->n_energies, c->kpad, c->nt, c->nt_alloc, p->dt, c->d_phase, s0);
     if (e == hipSuccess) e = hipDeviceSynchronize();
     if (e != hipSuccess) {
@@ -392,6 +401,8 @@ scivr_status scivr_propagate(scivr_ctx *ctx, int32_t step_begin, int32_t step_en
     a.scal = ctx->d_scal;
     a.Mst = ctx->d_M;
     a.amp = ctx->d_amp;
+    a.amp16 = ctx->d_amp16;
+    a.plane = (int64_t)ctx->nt16 * ctx->npad;
     a.n = ctx->n_traj;
     a.npad = ctx->npad;
     a.step_begin = step_begin;
@@ -399,7 +410,7 @@ scivr_status scivr_propagate(scivr_ctx *ctx, int32_t step_begin, int32_t step_en
     a.n_steps = ctx->n_steps;
     a.check_every = ctx->check_every;
     Timed tm(ctx, s, 1);
-    HIPCALL(ctx, launch_traj_fp64(ctx->F, a, s));
+    HIPCALL(ctx, launch_traj(ctx->F, ctx->precision == SCIVR_PRECISION_MIXED, a, s));
     tm.done();
     ctx->steps_done = step_end;
     ctx->accumulated = false;
@@ -414,28 +425,49 @@ scivr_status scivr_accumulate_spectrum(scivr_ctx *ctx, void *stream)
                     ctx->n_steps);
     if (ctx->accumulated) return fail(ctx, SCIVR_ESTATE, "batch already accumulated");
     hipStream_t s = (hipStream_t)stream;
-    HIPCALL(ctx, launch_weights(ctx->d_scal + SC_GOOD * ctx->npad, ctx->d_logrho, ctx->host_prob.F_log_2pi,
-                                ctx->n_traj, ctx->npad, ctx->d_weight, ctx->d_ngood, s));
-    GemmArgs g;
-    g.amp = ctx->d_amp;
-    g.phase = ctx->d_phase;
-    g.weight = ctx->d_weight;
-    g.part_spec = ctx->d_part_spec;
-    g.part_contrib = ctx->d_part_contrib;
-    g.npad = ctx->npad;
-    g.kpad = ctx->kpad;
-    g.nt_pad = ctx->nt_pad;
+    HIPCALL(ctx, launch_weights(ctx->d_scal + SC_GOOD * ctx->npad, ctx->d_scal + SC_ESCALE * ctx->npad,
+                                ctx->d_logrho, ctx->host_prob.F_log_2pi, ctx->n_traj, ctx->npad, ctx->d_weight,
+                                ctx->d_ngood, s));
     // only the row tiles that hold trajectories of this batch
-    g.row_tiles = (int32_t)((ctx->n_traj + GEMM_BM - 1) / GEMM_BM);
-    g.col_tiles = ctx->col_tiles;
-    {
+    const int32_t row_tiles = (int32_t)((ctx->n_traj + GEMM_BM - 1) / GEMM_BM);
+    if (ctx->precision == SCIVR_PRECISION_MIXED) {
+        GemmF16Args g;
+        g.amp16 = ctx->d_amp16;
+        g.plane = (int64_t)ctx->nt16 * ctx->npad;
+        g.weight = ctx->d_weight;
+        g.part_spec = ctx->d_part_spec;
+        g.part_contrib = ctx->d_part_contrib;
+        g.npad = ctx->npad;
+        g.kpad = ctx->kpad;
+        g.nt_pad = ctx->nt16;
+        g.K = ctx->n_energies;
+        g.row_tiles = row_tiles;
+        g.col_tiles = ctx->col_tiles;
+        g.e_min = ctx->e_min;
+        g.de = (ctx->e_max - ctx->e_min) / (double)(ctx->n_energies - 1);
+        g.dt = ctx->dt;
+        Timed tm(ctx, s, 2);
+        HIPCALL(ctx, launch_fourier_f16(g, s));
+        tm.done();
+    } else {
+        GemmArgs g;
+        g.amp = ctx->d_amp;
+        g.phase = ctx->d_phase;
+        g.weight = ctx->d_weight;
+        g.part_spec = ctx->d_part_spec;
+        g.part_contrib = ctx->d_part_contrib;
+        g.npad = ctx->npad;
+        g.kpad = ctx->kpad;
+        g.nt_pad = ctx->nt_pad;
+        g.row_tiles = row_tiles;
+        g.col_tiles = ctx->col_tiles;
         Timed tm(ctx, s, 2);
         HIPCALL(ctx, launch_fourier_fp64(g, s));
         tm.done();
     }
     {
         Timed tm(ctx, s, 3);
-        HIPCALL(ctx, launch_spectrum_reduce(ctx->d_part_spec, g.row_tiles, ctx->n_energies, ctx->kpad, ctx->d_total,
+        HIPCALL(ctx, launch_spectrum_reduce(ctx->d_part_spec, row_tiles, ctx->n_energies, ctx->kpad, ctx->d_total,
                                             s));
         HIPCALL(ctx, launch_contrib_reduce(ctx->d_part_contrib, ctx->kpad / 64, ctx->d_weight, ctx->n_traj,
                                            ctx->npad, ctx->d_contrib, s));
@@ -541,13 +573,34 @@ scivr_status scivr_read_amplitudes(scivr_ctx *ctx, int64_t j0, int64_t count, do
                     (long long)(j0 + count));
     HIPCALL(ctx, hipDeviceSynchronize());
     const int nt = ctx->nt;
-    std::vector<double2> buf((size_t)nt * count);
-    HIPCALL(ctx, hipMemcpy2D(buf.data(), count * sizeof(double2), ctx->d_amp + j0, ctx->npad * sizeof(double2),
-                             count * sizeof(double2), nt, hipMemcpyDeviceToHost));
+    if (ctx->precision != SCIVR_PRECISION_MIXED) {
+        std::vector<double2> buf((size_t)nt * count);
+        HIPCALL(ctx, hipMemcpy2D(buf.data(), count * sizeof(double2), ctx->d_amp + j0, ctx->npad * sizeof(double2),
+                                 count * sizeof(double2), nt, hipMemcpyDeviceToHost));
+        for (int64_t j = 0; j < count; ++j)
+            for (int c = 0; c < nt; ++c) {
+                amp[(j * nt + c) * 2] = buf[(size_t)c * count + j].x;
+                amp[(j * nt + c) * 2 + 1] = buf[(size_t)c * count + j].y;
+            }
+        return SCIVR_OK;
+    }
+    // mixed form: planes [nt16 / 8][npad][8] of FP16 hi/lo, scaled by 2^escale_j
+    const int64_t nb = ctx->nt16 / 8, plane = (int64_t)ctx->nt16 * ctx->npad;
+    std::vector<_Float16> buf((size_t)4 * nb * count * 8);
+    for (int pl = 0; pl < 4; ++pl)
+        HIPCALL(ctx, hipMemcpy2D(buf.data() + (size_t)pl * nb * count * 8, count * 8 * sizeof(_Float16),
+                                 ctx->d_amp16 + pl * plane + j0 * 8, ctx->npad * 8 * sizeof(_Float16),
+                                 count * 8 * sizeof(_Float16), nb, hipMemcpyDeviceToHost));
+    std::vector<double> esc(count);
+    HIPCALL(ctx, hipMemcpy(esc.data(), ctx->d_scal + SC_ESCALE * ctx->npad + j0, count * sizeof(double),
+                           hipMemcpyDeviceToHost));
+    auto at = [&](int pl, int64_t j, int c) {
+        return (double)(float)buf[(((size_t)pl * nb + c / 8) * count + j) * 8 + c % 8];
+    };
     for (int64_t j = 0; j < count; ++j)
         for (int c = 0; c < nt; ++c) {
-            amp[(j * nt + c) * 2] = buf[(size_t)c * count + j].x;
-            amp[(j * nt + c) * 2 + 1] = buf[(size_t)c * count + j].y;
+            amp[(j * nt + c) * 2] = ldexp(at(0, j, c) + at(1, j, c), -(int)esc[j]);
+            amp[(j * nt + c) * 2 + 1] = ldexp(at(2, j, c) + at(3, j, c), -(int)esc[j]);
         }
     return SCIVR_OK;
 }

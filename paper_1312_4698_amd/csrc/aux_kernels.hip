@@ -89,17 +89,19 @@ __global__ void phase_table_kernel(double e_min, double e_max, int K, int kpad, 
     phase[idx] = v;
 }
 
-// weight_j = good_j exp(-ln rho_j - F ln 2 pi) for j < n, 0 in the padding; counts good.
-__global__ void weights_kernel(const double *__restrict__ good_row, const double *__restrict__ logrho,
-                               double F_log_2pi, int64_t n, int64_t npad, double *weight,
-                               unsigned long long *n_good)
+// weight_j = good_j exp(-ln rho_j - F ln 2 pi) 4^-e_j for j < n, 0 in the padding
+// (e_j: the power-of-two scale the mixed form applied to trajectory j's
+// amplitudes, 0 in the FP64 form); counts good trajectories.
+__global__ void weights_kernel(const double *__restrict__ good_row, const double *__restrict__ escale_row,
+                               const double *__restrict__ logrho, double F_log_2pi, int64_t n, int64_t npad,
+                               double *weight, unsigned long long *n_good)
 {
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     bool g = false;
     if (j < npad) {
         double w = 0.0;
         if (j < n && good_row[j] != 0.0) {
-            w = exp(-logrho[j] - F_log_2pi);
+            w = ldexp(exp(-logrho[j] - F_log_2pi), -2 * (int)escale_row[j]);
             g = true;
         }
         weight[j] = w;
@@ -158,11 +160,11 @@ hipError_t launch_phase_table(double e_min, double e_max, int K, int kpad, int n
     return hipGetLastError();
 }
 
-hipError_t launch_weights(const double *scal_good_row, const double *logrho, double F_log_2pi, int64_t n,
-                          int64_t npad, double *weight, unsigned long long *n_good, hipStream_t s)
+hipError_t launch_weights(const double *good_row, const double *escale_row, const double *logrho, double F_log_2pi,
+                          int64_t n, int64_t npad, double *weight, unsigned long long *n_good, hipStream_t s)
 {
-    hipLaunchKernelGGL(weights_kernel, dim3(blocks_for(npad, 256)), dim3(256), 0, s, scal_good_row, logrho, F_log_2pi,
-                       n, npad, weight, n_good);
+    hipLaunchKernelGGL(weights_kernel, dim3(blocks_for(npad, 256)), dim3(256), 0, s, good_row, escale_row, logrho,
+                       F_log_2pi, n, npad, weight, n_good);
     return hipGetLastError();
 }
 

@@ -17,7 +17,9 @@ constexpr int GEMM_BN = 128;
 constexpr int GEMM_BK = 4;
 
 // Scalar per-trajectory state rows, structure of arrays [NSCAL][npad].
-enum ScalarRow { SC_S = 0, SC_THETA, SC_PREV_RE, SC_PREV_IM, SC_PHI, SC_GOOD, SC_DETM, SC_MAXDEV, NSCAL };
+enum ScalarRow {
+    SC_S = 0, SC_SCOMP, SC_THETA, SC_PREV_RE, SC_PREV_IM, SC_PHI, SC_GOOD, SC_DETM, SC_MAXDEV, SC_ESCALE, NSCAL
+};
 
 // Trajectory-independent constants, read with uniform (scalar) loads.
 struct ProblemDev {
@@ -40,9 +42,26 @@ struct TrajArgs {
     double *p, *q;          // [F][npad] state
     double *scal;           // [NSCAL][npad]
     double *Mst;            // [(2F)^2][npad], element r*2F + c
-    double2 *amp;           // [nt_pad][npad]
+    double2 *amp;           // FP64 form: [nt_alloc][npad]
+    _Float16 *amp16;        // mixed form: 4 planes [nt_alloc / 8][npad][8]
+    int64_t plane;          // elements per plane of amp16
     int64_t n, npad;
     int32_t step_begin, step_end, n_steps, check_every;
+};
+
+// Time samples per FP16 MFMA k-step of the mixed-form Fourier GEMM.
+constexpr int GEMM16_BK = 32;
+
+struct GemmF16Args {
+    const _Float16 *amp16;  // planes re_hi, re_lo, im_hi, im_lo: [nt_alloc / 8][npad][8]
+    int64_t plane;
+    const double *weight;
+    double *part_spec;
+    double *part_contrib;
+    int64_t npad;
+    int32_t kpad, nt_pad, K;
+    int32_t row_tiles, col_tiles;
+    double e_min, de, dt;
 };
 
 struct GemmArgs {
@@ -56,14 +75,15 @@ struct GemmArgs {
     int32_t row_tiles, col_tiles;
 };
 
-hipError_t launch_traj_fp64(int F, const TrajArgs &a, hipStream_t s);
+hipError_t launch_traj(int F, bool mixed, const TrajArgs &a, hipStream_t s);
 hipError_t launch_sample_husimi(const ProblemDev *P, int F, uint64_t seed, uint64_t first, int64_t n, int64_t npad,
                                 double *p0, double *q0, double *logrho, hipStream_t s);
 hipError_t launch_phase_table(double e_min, double e_max, int K, int kpad, int nt, int nt_pad, double dt,
                               double2 *phase, hipStream_t s);
-hipError_t launch_weights(const double *scal, const double *logrho, double F_log_2pi, int64_t n, int64_t npad,
-                          double *weight, unsigned long long *n_good, hipStream_t s);
+hipError_t launch_weights(const double *good_row, const double *escale_row, const double *logrho, double F_log_2pi,
+                          int64_t n, int64_t npad, double *weight, unsigned long long *n_good, hipStream_t s);
 hipError_t launch_fourier_fp64(const GemmArgs &a, hipStream_t s);
+hipError_t launch_fourier_f16(const GemmF16Args &a, hipStream_t s);
 hipError_t launch_spectrum_reduce(const double *part_spec, int row_tiles, int K, int kpad, double *total,
                                   hipStream_t s);
 hipError_t launch_contrib_reduce(const double *part_contrib, int ctiles, const double *weight, int64_t n,

@@ -31,6 +31,8 @@
 // a time-major [t][trajectory] matrix, the left operand of the Fourier GEMM.
 #include <math.h>
 
+#include <type_traits>
+
 #include "scivr_internal.h"
 
 namespace scivr {
@@ -43,8 +45,6 @@ struct alignas(16) GroupLds {
     double T[F * RS];                  // one half (F rows) of the transposed monodromy matrix
     double pivM[N2];                   // pivot row of the real elimination
     double pivA[N2];                   // pivot row of the complex elimination (re, im interleaved)
-    double qv[F + (F & 1)], pv_mom[F + (F & 1)];  // the trajectory's q and p, one entry per owning lane
-    double pg[F + (F & 1)], ph[F + (F & 1)], pv[F + (F & 1)];
     unsigned long long slotM[N2];      // per-step argmax keys of the two eliminations
     unsigned long long slotA[F + (F & 1)];
 };
@@ -189,15 +189,70 @@ __device__ inline void lu_det_complex(double (&ar)[N], double (&ai)[N], int pos,
 template <int F>
 constexpr int traj_waves() { return F <= 3 ? 4 : (F <= 6 ? 3 : (F <= 12 ? 2 : 1)); }
 
-template <int F>
-__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(traj_waves<F>(), 8)))
-traj_fp64_kernel(TrajArgs A, const ProblemDev *__restrict__ P0)
+// Kahan-compensated running sum (used for the FP32 action of the mixed form).
+struct Kahan {
+    float s = 0.f, c = 0.f;
+    __device__ void add(float x)
+    {
+        const float y = x - c;
+        const float t = s + y;
+        c = (t - s) - y;
+        s = t;
+    }
+    __device__ double value() const { return (double)s - (double)c; }
+};
+
+template <bool MIXED>
+struct Action;
+template <>
+struct Action<false> {
+    double s = 0.0;
+    __device__ void add(double x) { s += x; }
+    __device__ double value() const { return s; }
+    __device__ void load(double v, double) { s = v; }
+    __device__ double hi() const { return s; }
+    __device__ double lo() const { return 0.0; }
+};
+template <>
+struct Action<true> {
+    Kahan k;
+    __device__ void add(double x) { k.add((float)x); }
+    __device__ double value() const { return k.value(); }
+    __device__ void load(double v, double comp)
+    {
+        k.s = (float)v;
+        k.c = (float)comp;
+    }
+    __device__ double hi() const { return (double)k.s; }
+    __device__ double lo() const { return (double)k.c; }
+};
+
+// Split x into FP16 hi + lo with x ~ hi + lo to about 22 bits.
+__device__ inline void split_f16(float x, _Float16 &hi, _Float16 &lo)
 {
+    hi = (_Float16)x;
+    lo = (_Float16)(x - (float)hi);
+}
+
+// The trajectory kernel.  MIXED = false: every trajectory quantity in FP64.
+// MIXED = true: the trajectory (p, q), the potential, gradient and Hessian
+// diagonal and the action (Kahan-compensated) in FP32; the tangent columns,
+// det(A), det(M) and the phase branch stay in FP64; the amplitude, scaled by a
+// per-trajectory power of two 2^e (e ~ -log2 |<chi|z_0>|, 0 <= e <= 12) so that
+// it sits well inside FP16 range, is stored as FP16 hi/lo planes
+// [re_hi, re_lo, im_hi, im_lo][t / 8][trajectory][t % 8] for the FP16 GEMM.
+template <int F, bool MIXED>
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(traj_waves<F>(), 8)))
+traj_kernel(TrajArgs A, const ProblemDev *__restrict__ P0)
+{
+    typedef typename std::conditional<MIXED, float, double>::type R;
     constexpr int N2 = 2 * F;
     constexpr int TPW = 64 / F;
     constexpr int RS = GroupLds<F>::RS;
     __shared__ GroupLds<F> lds_all[TPW];
     __shared__ double lam_lds[F * F];  // coupling matrix, shared by the wave's groups
+    __shared__ R qv_all[TPW][F + (F & 1)], pm_all[TPW][F + (F & 1)];
+    __shared__ R pg_all[TPW][F + (F & 1)], ph_all[TPW][F + (F & 1)], pv_all[TPW][F + (F & 1)];
 
     const int lane = threadIdx.x;
     const ProblemDev *__restrict__ P = P0;
@@ -209,20 +264,25 @@ traj_fp64_kernel(TrajArgs A, const ProblemDev *__restrict__ P0)
     if (grp >= TPW) return;
     const int c = lane - grp * F;  // degree of freedom owned by this lane
     GroupLds<F> &L = lds_all[grp];
+    R *qv = qv_all[grp], *pm = pm_all[grp], *pg = pg_all[grp], *phd = ph_all[grp], *pv = pv_all[grp];
+    (void)pg;
     const int64_t j = (int64_t)blockIdx.x * TPW + grp;
     const bool live = j < A.n;
     const int64_t jr = live ? j : 0;
     const int64_t NP = A.npad;
 
     // constants of the lane's own mode c
-    const double kc = P->k[c], Dc = P->D[c], ac = P->a[c];
+    const R kc = (R)P->k[c], Dc = (R)P->D[c], ac = (R)P->a[c];
     const double sgc = P->sqrt_gamma[c], isgc = P->inv_sqrt_gamma[c];
 
     // pc, qc: the trajectory's momentum and position of mode c (the group's
     // full p and q live in LDS); columns c ("P": d/dp0_c) and F + c ("Q":
     // d/dq0_c) of M, split into their p and q halves.
     double dpP[F], dqP[F], dpQ[F], dqQ[F];
-    double pc, qc, S, theta, prev_r, prev_i, phi, detM, maxdev;
+    R pc, qc;
+    Action<MIXED> S;
+    double theta, prev_r, prev_i, phi, detM, maxdev;
+    int escale = 0;  // amplitude scale exponent (mixed form)
     bool good;
     if (A.step_begin == 0) {
 #pragma unroll
@@ -232,9 +292,9 @@ traj_fp64_kernel(TrajArgs A, const ProblemDev *__restrict__ P0)
             dpQ[i] = 0.0;
             dqQ[i] = (i == c) ? 1.0 : 0.0;
         }
-        pc = A.p0[c * NP + jr];
-        qc = A.q0[c * NP + jr];
-        S = theta = phi = prev_i = 0.0;
+        pc = (R)A.p0[c * NP + jr];
+        qc = (R)A.q0[c * NP + jr];
+        theta = phi = prev_i = 0.0;
         prev_r = 1.0;  // det(A) = 1 at t = 0
         detM = 1.0;
         maxdev = 0.0;
@@ -247,9 +307,9 @@ traj_fp64_kernel(TrajArgs A, const ProblemDev *__restrict__ P0)
             dpQ[i] = A.Mst[(int64_t)(i * N2 + F + c) * NP + jr];
             dqQ[i] = A.Mst[(int64_t)((F + i) * N2 + F + c) * NP + jr];
         }
-        pc = A.p[c * NP + jr];
-        qc = A.q[c * NP + jr];
-        S = A.scal[SC_S * NP + jr];
+        pc = (R)A.p[c * NP + jr];
+        qc = (R)A.q[c * NP + jr];
+        S.load(A.scal[SC_S * NP + jr], A.scal[SC_SCOMP * NP + jr]);
         theta = A.scal[SC_THETA * NP + jr];
         prev_r = A.scal[SC_PREV_RE * NP + jr];
         prev_i = A.scal[SC_PREV_IM * NP + jr];
@@ -257,32 +317,59 @@ traj_fp64_kernel(TrajArgs A, const ProblemDev *__restrict__ P0)
         good = A.scal[SC_GOOD * NP + jr] != 0.0;
         detM = A.scal[SC_DETM * NP + jr];
         maxdev = A.scal[SC_MAXDEV * NP + jr];
+        escale = (int)A.scal[SC_ESCALE * NP + jr];
     }
-    L.qv[c] = qc;
-    L.pv_mom[c] = pc;
+    qv[c] = qc;
+    pm[c] = pc;
     lds_order();
 
-    // amplitude <chi|p,q> e^{i(S + phi)} of the published state (zero when bad)
-    auto amplitude = [&](auto PP) -> double2 {
-        double ex = 0.0, ph = 0.0;
+    // exponent of <chi|p,q> of the published state
+    auto overlap = [&](auto PP, double &ph) -> double {
+        double ex = 0.0;
+        ph = 0.0;
 #pragma unroll
         for (int i = 0; i < F; ++i) {
-            const double qi = L.qv[i], pi = L.pv_mom[i];
+            const double qi = (double)qv[i], pi = (double)pm[i];
             const double dqe = PP->q_eq[i] - qi;
             const double dpe = PP->p_eq[i] - pi;
             ex += -0.25 * PP->gamma[i] * dqe * dqe - dpe * dpe * PP->inv4gamma[i];
             ph += 0.5 * dqe * (PP->p_eq[i] + pi);
         }
+        return ex;
+    };
+    // store the amplitude <chi|p,q> e^{i(S + phi)} of time sample t (zero when bad)
+    auto store_amplitude = [&](auto PP, int t) {
+        double ph;
+        const double ex = overlap(PP, ph);
         double s, co;
-        dsincos(ph + S + phi, &PP->mc, &s, &co);
-        const double mag = dexp(ex, &PP->mc);
-        double2 r;
-        r.x = good ? mag * co : 0.0;
-        r.y = good ? mag * s : 0.0;
-        return r;
+        dsincos(ph + S.value() + phi, &PP->mc, &s, &co);
+        if constexpr (!MIXED) {
+            const double mag = dexp(ex, &PP->mc);
+            double2 r;
+            r.x = good ? mag * co : 0.0;
+            r.y = good ? mag * s : 0.0;
+            A.amp[(int64_t)t * NP + jr] = r;
+        } else {
+            const double mag = ldexp(dexp(ex, &PP->mc), escale);
+            const float re = good ? (float)(mag * co) : 0.f, im = good ? (float)(mag * s) : 0.f;
+            _Float16 h[4];
+            split_f16(re, h[0], h[1]);
+            split_f16(im, h[2], h[3]);
+            const int64_t e = ((int64_t)(t >> 3) * NP + jr) * 8 + (t & 7);
+#pragma unroll
+            for (int pl = 0; pl < 4; ++pl) A.amp16[pl * A.plane + e] = h[pl];
+        }
     };
 
-    if (A.step_begin == 0 && live && c == 0) A.amp[jr] = amplitude(P);
+    if (A.step_begin == 0 && c == 0) {
+        if constexpr (MIXED) {
+            double ph;
+            const double ex0 = overlap(P, ph);
+            // 2^escale ~ 1/|<chi|z_0>|, exact power of two, bounded so |amp| 2^escale < 2^12
+            escale = (int)fmin(fmax(floor(-ex0 * 1.4426950408889634), 0.0), 12.0);
+        }
+        if (live) store_amplitude(P, 0);
+    }
 
     for (int step = A.step_begin; step < A.step_end; ++step) {
         ConstProblem Ps = opaque(P0);
@@ -292,47 +379,51 @@ traj_fp64_kernel(TrajArgs A, const ProblemDev *__restrict__ P0)
             // ---- drift ----
             const double h = Pk->hd[s];
             if (c == 0) {  // the action is carried by lane 0 only
-                double kin = 0.0;
+                R kin = 0;
 #pragma unroll
                 for (int i = 0; i < F; ++i) {
-                    const double pi = L.pv_mom[i];
-                    kin += 0.5 * pi * pi;
+                    const R pi = pm[i];
+                    kin += (R)0.5 * pi * pi;
                 }
-                S = fma(h, kin, S);
+                S.add(h * (double)kin);
             }
-            qc = fma(h, pc, qc);
+            qc = fma((R)h, pc, qc);
 #pragma unroll
             for (int i = 0; i < F; ++i) {
                 dqP[i] = fma(h, dpP[i], dqP[i]);
                 dqQ[i] = fma(h, dpQ[i], dqQ[i]);
             }
             lds_order();
-            L.qv[c] = qc;
+            qv[c] = qc;
             lds_order();
             if (s == 3) break;
             // ---- kick: mode c's terms, shared through LDS ----
             const double hk = Pk->hc[s];
-            double q[F];
+            R q[F];
 #pragma unroll
-            for (int i = 0; i < F; ++i) q[i] = L.qv[i];
-            double sm = 0.0;
+            for (int i = 0; i < F; ++i) q[i] = qv[i];
+            R sm = 0;
 #pragma unroll
-            for (int i = 0; i < F; ++i) sm = fma(lam_lds[c * F + i], q[i] * q[i], sm);
-            const double e = dexp(-ac * qc, &Pk->mc);
-            const double one_e = 1.0 - e;
-            const double gc = kc * qc + 2.0 * Dc * ac * e * one_e + 2.0 * qc * sm;
-            const double hc = kc + 2.0 * Dc * ac * ac * e * (2.0 * e - 1.0) + 2.0 * sm;
-            const double vc = 0.5 * kc * qc * qc + Dc * one_e * one_e + 0.5 * qc * qc * sm;
-            pc = fma(-hk, gc, pc);
-            L.ph[c] = hc;
-            L.pv[c] = vc;
-            L.pv_mom[c] = pc;
+            for (int i = 0; i < F; ++i) sm = fma((R)lam_lds[c * F + i], q[i] * q[i], sm);
+            R e;
+            if constexpr (MIXED)
+                e = expf(-ac * qc);
+            else
+                e = dexp(-ac * qc, &Pk->mc);
+            const R one_e = (R)1 - e;
+            const R gc = kc * qc + (R)2 * Dc * ac * e * one_e + (R)2 * qc * sm;
+            const R hc = kc + (R)2 * Dc * ac * ac * e * ((R)2 * e - (R)1) + (R)2 * sm;
+            const R vc = (R)0.5 * kc * qc * qc + Dc * one_e * one_e + (R)0.5 * qc * qc * sm;
+            pc = fma(-(R)hk, gc, pc);
+            phd[c] = hc;
+            pv[c] = vc;
+            pm[c] = pc;
             lds_order();
             if (c == 0) {
-                double V = 0.0;
+                R V = 0;
 #pragma unroll
-                for (int i = 0; i < F; ++i) V += L.pv[i];
-                S = fma(-hk, V, S);
+                for (int i = 0; i < F; ++i) V += pv[i];
+                S.add(-hk * (double)V);
             }
             // tangent kick, one column after the other: dp -= hk (h o dq + 4 q o Lambda (q o dq))
 #pragma unroll
@@ -342,7 +433,7 @@ traj_fp64_kernel(TrajArgs A, const ProblemDev *__restrict__ P0)
                 double u[F], w[F];
 #pragma unroll
                 for (int i = 0; i < F; ++i) {
-                    u[i] = q[i] * dq[i];
+                    u[i] = (double)q[i] * dq[i];
                     w[i] = 0.0;
                 }
 #pragma unroll
@@ -354,7 +445,8 @@ traj_fp64_kernel(TrajArgs A, const ProblemDev *__restrict__ P0)
                         w[jj] = fma(l, u[i], w[jj]);
                     }
 #pragma unroll
-                for (int i = 0; i < F; ++i) dp[i] = fma(-hk, fma(L.ph[i], dq[i], 4.0 * q[i] * w[i]), dp[i]);
+                for (int i = 0; i < F; ++i)
+                    dp[i] = fma(-hk, fma((double)phd[i], dq[i], 4.0 * (double)q[i] * w[i]), dp[i]);
             }
             lds_order();
         }
@@ -423,17 +515,18 @@ traj_fp64_kernel(TrajArgs A, const ProblemDev *__restrict__ P0)
             prev_r = dAr;
             prev_i = dAi;
             phi = 0.5 * (theta - Ps->sum_gamma * t);
-            if (!isfinite(phi) || !isfinite(S)) good = false;
-            if (live) A.amp[(int64_t)stp * NP + jr] = amplitude(Ps);
+            if (!isfinite(phi) || !isfinite(S.value())) good = false;
+            if (live) store_amplitude(Ps, stp);
         }
     }
 
     // ---- save the state for a later continuation and for inspection ----
     if (live) {
-        A.p[c * NP + jr] = pc;
-        A.q[c * NP + jr] = qc;
+        A.p[c * NP + jr] = (double)pc;
+        A.q[c * NP + jr] = (double)qc;
         if (c == 0) {
-            A.scal[SC_S * NP + jr] = S;
+            A.scal[SC_S * NP + jr] = S.hi();
+            A.scal[SC_SCOMP * NP + jr] = S.lo();
             A.scal[SC_THETA * NP + jr] = theta;
             A.scal[SC_PREV_RE * NP + jr] = prev_r;
             A.scal[SC_PREV_IM * NP + jr] = prev_i;
@@ -441,6 +534,7 @@ traj_fp64_kernel(TrajArgs A, const ProblemDev *__restrict__ P0)
             A.scal[SC_GOOD * NP + jr] = good ? 1.0 : 0.0;
             A.scal[SC_DETM * NP + jr] = detM;
             A.scal[SC_MAXDEV * NP + jr] = maxdev;
+            A.scal[SC_ESCALE * NP + jr] = (double)escale;
         }
 #pragma unroll
         for (int i = 0; i < F; ++i) {
@@ -452,39 +546,45 @@ traj_fp64_kernel(TrajArgs A, const ProblemDev *__restrict__ P0)
     }
 }
 
-template <int F>
+template <int F, bool MIXED>
 hipError_t launch_F(const TrajArgs &a, hipStream_t s)
 {
     constexpr int TPW = 64 / F;
     const int64_t blocks = (a.n + TPW - 1) / TPW;
     if (blocks <= 0) return hipSuccess;
-    hipLaunchKernelGGL(traj_fp64_kernel<F>, dim3((unsigned)blocks), dim3(64), 0, s, a, a.prob);
+    hipLaunchKernelGGL((traj_kernel<F, MIXED>), dim3((unsigned)blocks), dim3(64), 0, s, a, a.prob);
     return hipGetLastError();
+}
+
+template <bool MIXED>
+hipError_t launch_any(int F, const TrajArgs &a, hipStream_t s)
+{
+    switch (F) {
+    case 1: return launch_F<1, MIXED>(a, s);
+    case 2: return launch_F<2, MIXED>(a, s);
+    case 3: return launch_F<3, MIXED>(a, s);
+    case 4: return launch_F<4, MIXED>(a, s);
+    case 5: return launch_F<5, MIXED>(a, s);
+    case 6: return launch_F<6, MIXED>(a, s);
+    case 7: return launch_F<7, MIXED>(a, s);
+    case 8: return launch_F<8, MIXED>(a, s);
+    case 9: return launch_F<9, MIXED>(a, s);
+    case 10: return launch_F<10, MIXED>(a, s);
+    case 11: return launch_F<11, MIXED>(a, s);
+    case 12: return launch_F<12, MIXED>(a, s);
+    case 13: return launch_F<13, MIXED>(a, s);
+    case 14: return launch_F<14, MIXED>(a, s);
+    case 15: return launch_F<15, MIXED>(a, s);
+    case 16: return launch_F<16, MIXED>(a, s);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 }  // namespace
 
-hipError_t launch_traj_fp64(int F, const TrajArgs &a, hipStream_t s)
+hipError_t launch_traj(int F, bool mixed, const TrajArgs &a, hipStream_t s)
 {
-    switch (F) {
-    case 1: return launch_F<1>(a, s);
-    case 2: return launch_F<2>(a, s);
-    case 3: return launch_F<3>(a, s);
-    case 4: return launch_F<4>(a, s);
-    case 5: return launch_F<5>(a, s);
-    case 6: return launch_F<6>(a, s);
-    case 7: return launch_F<7>(a, s);
-    case 8: return launch_F<8>(a, s);
-    case 9: return launch_F<9>(a, s);
-    case 10: return launch_F<10>(a, s);
-    case 11: return launch_F<11>(a, s);
-    case 12: return launch_F<12>(a, s);
-    case 13: return launch_F<13>(a, s);
-    case 14: return launch_F<14>(a, s);
-    case 15: return launch_F<15>(a, s);
-    case 16: return launch_F<16>(a, s);
-    default: return hipErrorInvalidValue;
-    }
+    return mixed ? launch_any<true>(F, a, s) : launch_any<false>(F, a, s);
 }
 
 }  // namespace scivr

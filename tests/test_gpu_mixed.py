@@ -1,0 +1,117 @@
+"""The mixed-precision form against the FP64 oracle and the FP64 GPU path.
+
+Mixed form: FP32 trajectory, potential, gradient, Hessian and Kahan-summed
+action; FP64 monodromy, det(A), det(M) and phase branch; split-FP16 MFMA
+Fourier GEMM with FP32 accumulation.  The bar is the one the method states
+for it: peak positions within 1 cm^-1 of the FP64 result, with the spectrum
+and amplitudes close at the level FP32 rounding explains.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1312_4698_amd import inputs, peaks
+from tests import _parity
+
+pytestmark = pytest.mark.gpu
+CM = inputs.CM1_PER_HARTREE
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def scivr():
+    from paper_1312_4698_amd import scivr as S
+    S.load()
+    return S
+
+
+def _run(S, prob, seed, n):
+    ctx = S.Context(prob, max_traj=n)
+    ctx.run(seed=seed, n_traj=n)
+    I, ng, nt = ctx.read_spectrum()
+    return ctx, I, ng
+
+
+@pytest.mark.parametrize("F,n,ns,K,emax", [(2, 700, 600, 300, 0.05), (6, 300, 500, 257, 0.1)])
+def test_mixed_matches_oracle(scivr, oracle_mod, F, n, ns, K, emax):
+    O = oracle_mod
+    _say(f"[mixed] F={F} n={n} steps={ns} K={K}")
+    prob = inputs.morse_quartic(F, F, n_steps=ns, n_energies=K, e_max=emax,
+                                precision=inputs.PRECISION_MIXED)
+    ctx, I, ng = _run(scivr, prob, 40 + F, n)
+    p0, q0, lr = O.sample_husimi(prob, 40 + F, n)
+    ora = O.run(prob, p0, q0, lr)
+    st = ctx.read_state()
+    flags_o = np.array([ora.state(j).good for j in range(n)])
+    agree = np.mean(flags_o == st["good"].astype(bool))
+    _say(f"[mixed] n_good gpu={ng} oracle={ora.n_good} flag agreement={agree:.4f}")
+    assert agree > 0.97
+    # regular trajectories: FP32 trajectory state within 1e-4 relative (scaled coordinates)
+    sg = np.sqrt(prob.gamma)
+    errs = []
+    for j in range(n):
+        so = ora.state(j)
+        if not (so.good and st["good"][j]):
+            continue
+        if np.linalg.norm(_parity.scaled_monodromy(prob, so.M)) > 1e2:
+            continue
+        xg = np.concatenate([sg * st["q"][:, j], st["p"][:, j] / sg])
+        xo = np.concatenate([sg * so.q, so.p / sg])
+        errs.append(np.max(np.abs(xg - xo)) / max(1.0, np.max(np.abs(xo))))
+    _say(f"[mixed] regular trajectories {len(errs)} worst state error {max(errs):.2e}")
+    assert len(errs) > n // 3 and max(errs) < 1e-4
+    # spectrum: relative error at the FP32 level, peaks within 1 cm^-1
+    T = prob.total_time
+    E = prob.energies()
+    rel = np.max(np.abs(I - ora.spectrum)) / np.max(ora.spectrum)
+    pr = peaks.find_peaks(E, ora.spectrum, T)
+    pt = peaks.find_peaks(E, I, T)
+    worst, missing = peaks.peak_errors(pr, pt, tol=20 / CM)
+    _say(f"[mixed] spectrum rel err {rel:.2e}; {len(pr)} peaks, worst shift {worst * CM:.3f} cm^-1, missing {missing}")
+    assert missing == 0 and worst * CM < 1.0
+    assert rel < 2e-2
+    # amplitudes reconstructed from the FP16 planes
+    amp_o = O.run(prob, p0[:, :3], q0[:, :3], lr[:3], want_amps=True).amps
+    amp_g = ctx.read_amplitudes(0, 3)
+    for j in range(3):
+        if st["good"][j] and ora.state(j).good:
+            scale = np.max(np.abs(amp_o[j]))
+            assert np.max(np.abs(amp_g[j] - amp_o[j])) < 1e-3 * scale
+    ctx.close()
+
+
+def test_mixed_harmonic_peak_exact(scivr):
+    prob = inputs.harmonic([2000.0, 3100.0], n_steps=2048, dt=10.0, e_min=0.0, e_max=0.05, n_energies=512)
+    prob = prob.replace(precision=inputs.PRECISION_MIXED)
+    e0 = prob.omega.sum() / 2
+    fine = prob.replace(e_min=e0 - 2e-5, e_max=e0 + 2e-5, n_energies=201)
+    ctx, I, ng = _run(scivr, fine, 3, 256)
+    ep = fine.energies()[int(np.argmax(I))]
+    assert abs(ep - e0) * CM < 0.1
+    c = ctx.read_contributions()
+    assert c.std() / c.mean() < 2e-3
+    ctx.close()
+
+
+def test_mixed_vs_fp64_gpu_same_samples(scivr):
+    """Same Husimi points through both GPU forms (F=9 shape, reduced size)."""
+    prob64 = inputs.morse_quartic(9, 9, n_steps=1024, n_energies=1024, e_max=0.1)
+    prob32 = prob64.replace(precision=inputs.PRECISION_MIXED)
+    n = 4096
+    c64, I64, ng64 = _run(scivr, prob64, 77, n)
+    c32, I32, ng32 = _run(scivr, prob32, 77, n)
+    T = prob64.total_time
+    E = prob64.energies()
+    pr = peaks.find_peaks(E, I64, T)
+    pt = peaks.find_peaks(E, I32, T)
+    worst, missing = peaks.peak_errors(pr, pt, tol=20 / CM)
+    _say(f"[mixed F9] good {ng64} vs {ng32}; {len(pr)} peaks, worst {worst * CM:.3f} cm^-1, missing {missing}")
+    assert missing == 0 and worst * CM < 1.0
+    assert abs(ng64 - ng32) < 0.02 * n
+    c64.close()
+    c32.close()
