@@ -11,51 +11,13 @@
 #include <string>
 #include <vector>
 
-#include "scivr.h"
-#include "scivr_internal.h"
+#include "ctx.h"
 
 using namespace scivr;
 
-struct EventPair {
-    hipEvent_t a, b;
-    int kind;
-};
+namespace scivr {
 
-struct scivr_ctx {
-    int device = 0;
-    int F = 0;
-    int32_t n_steps = 0, n_energies = 0, check_every = 1, precision = 0;
-    double dt = 0, e_min = 0, e_max = 0, det_tol = 0;
-    int64_t max_traj = 0, npad = 0;
-    int32_t nt = 0, nt_pad = 0, nt_alloc = 0, kpad = 0, row_tiles = 0, col_tiles = 0;
-
-    ProblemDev host_prob{};
-    ProblemDev *d_prob = nullptr;
-    double *d_p0 = nullptr, *d_q0 = nullptr, *d_logrho = nullptr;
-    double *d_p = nullptr, *d_q = nullptr, *d_scal = nullptr, *d_M = nullptr;
-    double2 *d_amp = nullptr, *d_phase = nullptr;  // FP64 form
-    _Float16 *d_amp16 = nullptr;                    // mixed form: 4 planes [nt16 / 8][npad][8]
-    int32_t nt16 = 0;                               // time samples per plane (multiple of 32)
-    double *d_weight = nullptr, *d_part_spec = nullptr, *d_part_contrib = nullptr, *d_contrib = nullptr;
-    double *d_total = nullptr;
-    unsigned long long *d_ngood = nullptr;
-
-    int64_t n_traj = 0;      // current batch size
-    int32_t steps_done = 0;
-    bool have_initial = false, accumulated = false;
-    int64_t n_total = 0;     // trajectories accumulated so far
-
-    bool device_error = false;
-    std::string err;
-
-    bool timing = false;
-    std::vector<EventPair> events;
-};
-
-namespace {
-
-scivr_status fail(scivr_ctx *c, scivr_status st, const char *fmt, ...) __attribute__((format(printf, 3, 4)));
-scivr_status fail(scivr_ctx *c, scivr_status st, const char *fmt, ...)
+scivr_status ctx_fail(scivr_ctx *c, scivr_status st, const char *fmt, ...)
 {
     if (c) {
         char buf[512];
@@ -69,21 +31,9 @@ scivr_status fail(scivr_ctx *c, scivr_status st, const char *fmt, ...)
     return st;
 }
 
-#define HIPCALL(ctx, expr)                                                                                  \
-    do {                                                                                                    \
-        hipError_t e_ = (expr);                                                                             \
-        if (e_ != hipSuccess)                                                                               \
-            return fail((ctx), SCIVR_EDEVICE, "%s failed: %s (%s:%d)", #expr, hipGetErrorString(e_), __FILE__, \
-                        __LINE__);                                                                          \
-    } while (0)
+}  // namespace scivr
 
-#define CHECK_CTX(ctx)                                                                        \
-    do {                                                                                      \
-        if (!(ctx)) return SCIVR_EINVAL;                                                      \
-        if ((ctx)->device_error) return SCIVR_EDEVICE;                                        \
-        hipError_t e_ = hipSetDevice((ctx)->device);                                          \
-        if (e_ != hipSuccess) return fail((ctx), SCIVR_EDEVICE, "hipSetDevice: %s", hipGetErrorString(e_)); \
-    } while (0)
+namespace {
 
 int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 
@@ -114,36 +64,6 @@ void free_all(scivr_ctx *c)
     c->events.clear();
 }
 
-// Bracket a launch with timing events when enabled.
-struct Timed {
-    scivr_ctx *c;
-    hipStream_t s;
-    int kind;
-    hipEvent_t a = nullptr, b = nullptr;
-    Timed(scivr_ctx *c_, hipStream_t s_, int k) : c(c_), s(s_), kind(k)
-    {
-        if (c->timing) {
-            if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
-                a = b = nullptr;
-                return;
-            }
-            (void)hipEventRecord(a, s);
-        }
-    }
-    void done()
-    {
-        if (a && b) {
-            (void)hipEventRecord(b, s);
-            c->events.push_back({a, b, kind});
-            a = b = nullptr;
-        }
-    }
-    ~Timed()
-    {
-        if (a) (void)hipEventDestroy(a);
-        if (b) (void)hipEventDestroy(b);
-    }
-};
 
 // Coefficients and reduction constants of the kernel's exp, sincos and atan2.
 // The split constants are pi/2 and ln 2 rounded to a double, then the
@@ -347,7 +267,7 @@ scivr_status scivr_sample_husimi(scivr_ctx *ctx, uint64_t seed, uint64_t first_i
 {
     CHECK_CTX(ctx);
     if (n_traj < 1 || n_traj > ctx->max_traj)
-        return fail(ctx, SCIVR_EINVAL, "n_traj %lld outside [1, %lld]", (long long)n_traj, (long long)ctx->max_traj);
+        return ctx_fail(ctx, SCIVR_EINVAL, "n_traj %lld outside [1, %lld]", (long long)n_traj, (long long)ctx->max_traj);
     hipStream_t s = (hipStream_t)stream;
     Timed tm(ctx, s, 0);
     HIPCALL(ctx, launch_sample_husimi(ctx->d_prob, ctx->F, seed, first_index, n_traj, ctx->npad, ctx->d_p0,
@@ -365,10 +285,10 @@ scivr_status scivr_set_initial(scivr_ctx *ctx, int64_t n_traj, const double *p0,
 {
     CHECK_CTX(ctx);
     if (n_traj < 1 || n_traj > ctx->max_traj)
-        return fail(ctx, SCIVR_EINVAL, "n_traj %lld outside [1, %lld]", (long long)n_traj, (long long)ctx->max_traj);
-    if (!p0 || !q0 || !log_density) return fail(ctx, SCIVR_EINVAL, "null initial-condition pointer");
+        return ctx_fail(ctx, SCIVR_EINVAL, "n_traj %lld outside [1, %lld]", (long long)n_traj, (long long)ctx->max_traj);
+    if (!p0 || !q0 || !log_density) return ctx_fail(ctx, SCIVR_EINVAL, "null initial-condition pointer");
     if (mem_kind != SCIVR_MEM_HOST && mem_kind != SCIVR_MEM_DEVICE)
-        return fail(ctx, SCIVR_EINVAL, "bad mem_kind %d", mem_kind);
+        return ctx_fail(ctx, SCIVR_EINVAL, "bad mem_kind %d", mem_kind);
     hipStream_t s = (hipStream_t)stream;
     const hipMemcpyKind kind = mem_kind == SCIVR_MEM_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
     const size_t row = (size_t)n_traj * sizeof(double), pitch = (size_t)ctx->npad * sizeof(double);
@@ -386,11 +306,11 @@ scivr_status scivr_set_initial(scivr_ctx *ctx, int64_t n_traj, const double *p0,
 scivr_status scivr_propagate(scivr_ctx *ctx, int32_t step_begin, int32_t step_end, void *stream)
 {
     CHECK_CTX(ctx);
-    if (!ctx->have_initial) return fail(ctx, SCIVR_ESTATE, "propagate before initial conditions");
+    if (!ctx->have_initial) return ctx_fail(ctx, SCIVR_ESTATE, "propagate before initial conditions");
     if (step_begin != ctx->steps_done)
-        return fail(ctx, SCIVR_ESTATE, "step_begin %d but %d steps done", step_begin, ctx->steps_done);
+        return ctx_fail(ctx, SCIVR_ESTATE, "step_begin %d but %d steps done", step_begin, ctx->steps_done);
     if (step_end <= step_begin || step_end > ctx->n_steps)
-        return fail(ctx, SCIVR_EINVAL, "step_end %d outside (%d, %d]", step_end, step_begin, ctx->n_steps);
+        return ctx_fail(ctx, SCIVR_EINVAL, "step_end %d outside (%d, %d]", step_end, step_begin, ctx->n_steps);
     hipStream_t s = (hipStream_t)stream;
     TrajArgs a;
     a.prob = ctx->d_prob;
@@ -421,9 +341,9 @@ scivr_status scivr_accumulate_spectrum(scivr_ctx *ctx, void *stream)
 {
     CHECK_CTX(ctx);
     if (!ctx->have_initial || ctx->steps_done != ctx->n_steps)
-        return fail(ctx, SCIVR_ESTATE, "accumulate needs a fully propagated batch (%d of %d steps)", ctx->steps_done,
+        return ctx_fail(ctx, SCIVR_ESTATE, "accumulate needs a fully propagated batch (%d of %d steps)", ctx->steps_done,
                     ctx->n_steps);
-    if (ctx->accumulated) return fail(ctx, SCIVR_ESTATE, "batch already accumulated");
+    if (ctx->accumulated) return ctx_fail(ctx, SCIVR_ESTATE, "batch already accumulated");
     hipStream_t s = (hipStream_t)stream;
     HIPCALL(ctx, launch_weights(ctx->d_scal + SC_GOOD * ctx->npad, ctx->d_scal + SC_ESCALE * ctx->npad,
                                 ctx->d_logrho, ctx->host_prob.F_log_2pi, ctx->n_traj, ctx->npad, ctx->d_weight,
@@ -527,7 +447,7 @@ static scivr_status copy_rows(scivr_ctx *ctx, double *dst, const double *src, in
 scivr_status scivr_read_initial(scivr_ctx *ctx, double *p0, double *q0, double *log_density)
 {
     CHECK_CTX(ctx);
-    if (!ctx->have_initial) return fail(ctx, SCIVR_ESTATE, "no initial conditions");
+    if (!ctx->have_initial) return ctx_fail(ctx, SCIVR_ESTATE, "no initial conditions");
     HIPCALL(ctx, hipDeviceSynchronize());
     scivr_status st;
     if (p0 && (st = copy_rows(ctx, p0, ctx->d_p0, ctx->F)) != SCIVR_OK) return st;
@@ -540,7 +460,7 @@ scivr_status scivr_read_state(scivr_ctx *ctx, double *p, double *q, double *S, d
                               double *detM, double *maxdev)
 {
     CHECK_CTX(ctx);
-    if (!ctx->have_initial || ctx->steps_done == 0) return fail(ctx, SCIVR_ESTATE, "no propagated state");
+    if (!ctx->have_initial || ctx->steps_done == 0) return ctx_fail(ctx, SCIVR_ESTATE, "no propagated state");
     HIPCALL(ctx, hipDeviceSynchronize());
     const int64_t n = ctx->n_traj, NP = ctx->npad;
     scivr_status st;
@@ -569,7 +489,7 @@ scivr_status scivr_read_amplitudes(scivr_ctx *ctx, int64_t j0, int64_t count, do
 {
     CHECK_CTX(ctx);
     if (!amp || j0 < 0 || count < 1 || j0 + count > ctx->n_traj)
-        return fail(ctx, SCIVR_EINVAL, "amplitude range [%lld, %lld) outside the batch", (long long)j0,
+        return ctx_fail(ctx, SCIVR_EINVAL, "amplitude range [%lld, %lld) outside the batch", (long long)j0,
                     (long long)(j0 + count));
     HIPCALL(ctx, hipDeviceSynchronize());
     const int nt = ctx->nt;
@@ -608,8 +528,8 @@ scivr_status scivr_read_amplitudes(scivr_ctx *ctx, int64_t j0, int64_t count, do
 scivr_status scivr_read_contributions(scivr_ctx *ctx, double *c)
 {
     CHECK_CTX(ctx);
-    if (!c) return fail(ctx, SCIVR_EINVAL, "null output");
-    if (!ctx->accumulated) return fail(ctx, SCIVR_ESTATE, "batch not accumulated");
+    if (!c) return ctx_fail(ctx, SCIVR_EINVAL, "null output");
+    if (!ctx->accumulated) return ctx_fail(ctx, SCIVR_ESTATE, "batch not accumulated");
     HIPCALL(ctx, hipDeviceSynchronize());
     HIPCALL(ctx, hipMemcpy(c, ctx->d_contrib, sizeof(double) * ctx->n_traj, hipMemcpyDeviceToHost));
     return SCIVR_OK;
