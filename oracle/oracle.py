@@ -276,6 +276,7 @@ class RunResult:
     contrib: Optional[np.ndarray]
     amps: Optional[np.ndarray]
     F: int
+    good_weight: float = 0.0
 
     def state(self, j: int) -> TrajState:
         return TrajState.decode(self.final_state[j], self.F)
@@ -295,15 +296,37 @@ def run(prob, p0, q0, logrho, *, want_state: bool = True, want_contrib: bool = T
     nt = op.struct.n_steps + 1
     spec = np.zeros(K)
     ng = ctypes.c_int64(0)
-    fs = np.zeros((n, state_size(F))) if want_state else None
+    fs = np.zeros((n, state_size(F)))  # always kept: the good flags enter the normalisation
     cb = np.zeros(n) if want_contrib else None
     am = np.zeros((n, nt, 2)) if want_amps else None
     rc = _load().orc_run(op.ref, n, _ptr(p0), _ptr(q0), _ptr(logrho), _ptr(spec), ctypes.byref(ng),
                          _ptr(fs), _ptr(cb), _ptr(am), int(n_threads))
     if rc != 0:
         raise MemoryError("oracle run failed to allocate")
+    good = fs[:, 2 * F + ST_GOOD] != 0.0
+    gw = good_weight(prob, p0, q0, logrho, good)
     I = np.zeros(K)
     _load().orc_normalise(op.ref, _ptr(spec), ng.value, _ptr(I))
+    if ng.value > 0:
+        I *= ng.value / gw
     amps = None if am is None else am[..., 0] + 1j * am[..., 1]
-    return RunResult(spec_sum=spec, n_good=int(ng.value), n_total=n, spectrum=I, final_state=fs,
-                     contrib=cb, amps=amps, F=F)
+    return RunResult(spec_sum=spec, n_good=int(ng.value), n_total=n, spectrum=I,
+                     final_state=fs if want_state else None, contrib=cb, amps=amps, F=F, good_weight=gw)
+
+
+def good_weight(prob, p0, q0, logrho, good) -> float:
+    """Sum over good trajectories of r_j = Husimi density / sampling density.
+
+    Eq. (11) divides by n_good, the number of good trajectories among points
+    drawn from the Husimi density, i.e. a Monte Carlo count of the good part
+    of that density.  Drawn from another density rho (the learned proposal),
+    the same count is estimated by sum_j good_j H(z_j) / rho(z_j); for Husimi
+    points every ratio is 1 and the sum is n_good.
+    """
+    g = np.asarray(prob.gamma, dtype=np.float64)[:, None]
+    xi2 = g * (np.asarray(q0) - np.asarray(prob.q_eq)[:, None]) ** 2
+    eta2 = (np.asarray(p0) - np.asarray(prob.p_eq)[:, None]) ** 2 / g
+    F = len(prob.gamma)
+    log_h = -F * np.log(2.0 * np.pi) - 0.5 * np.sum(xi2 + eta2, axis=0)
+    r = np.exp(log_h - np.asarray(logrho, dtype=np.float64))
+    return float(np.sum(r[np.asarray(good, dtype=bool)]))

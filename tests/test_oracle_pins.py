@@ -404,6 +404,32 @@ def test_harmonic_ground_state_spectrum_is_exact(oracle_mod):
     assert np.max(np.abs(r.spectrum - ref)) < 2e-3 * ref.max()
 
 
+def test_importance_weighted_normalisation(oracle_mod):
+    # Points from a wider, shifted Gaussian instead of the Husimi density: with
+    # weights 1/((2 pi)^F rho) and the good count taken as sum_j H_j / rho_j, the
+    # harmonic estimator keeps zero variance and reproduces the Husimi spectrum;
+    # for Husimi points that count is n_good itself.
+    O = oracle_mod
+    prob = inputs.harmonic([2000.0, 3100.0], n_steps=1024, dt=10.0, e_min=0.0, e_max=0.05, n_energies=400)
+    p0, q0, lr = O.sample_husimi(prob, 5, 64)
+    ref = O.run(prob, p0, q0, lr)
+    assert ref.good_weight == pytest.approx(ref.n_good, rel=1e-12)
+    F = prob.F
+    rng = np.random.default_rng(8)
+    sc, mu = 1.4, 0.3
+    x = mu + sc * rng.normal(size=(2 * F, 200))
+    sg = np.sqrt(prob.gamma)[:, None]
+    q1 = prob.q_eq[:, None] + x[:F] / sg
+    p1 = prob.p_eq[:, None] + x[F:] * sg
+    lr1 = -F * np.log(2 * np.pi) - 2 * F * np.log(sc) - 0.5 * np.sum((x - mu) ** 2, axis=0) / sc ** 2
+    r = O.run(prob, p1, q1, lr1)
+    assert r.n_good == 200
+    assert np.max(np.abs(r.spectrum - ref.spectrum)) < 2e-3 * ref.spectrum.max()
+    naive = r.spectrum * r.good_weight / r.n_good
+    assert abs(r.good_weight / r.n_good - 1.0) > 0.05  # the plain count would misnormalise
+    assert np.max(np.abs(naive - ref.spectrum)) > 0.05 * ref.spectrum.max()
+
+
 def test_displaced_harmonic_spectrum_poisson_closed_form(oracle_mod):
     O = oracle_mod
     om_cm = np.array([2000.0, 3100.0])
