@@ -41,9 +41,9 @@
 extern "C" {
 #endif
 
-#define SCIVR_ABI_VERSION 1
+#define SCIVR_ABI_VERSION 2
 /* Largest number of degrees of freedom of the FP64 trajectory kernel. */
-#define SCIVR_F_MAX 16
+#define SCIVR_F_MAX 32
 
 typedef int32_t scivr_status;
 #define SCIVR_OK 0
@@ -194,12 +194,109 @@ scivr_status scivr_read_contributions(scivr_ctx *ctx, double *c);
  * bracketed by HIP events on its stream.  scivr_kernel_times synchronises
  * and returns, per kernel kind, the number of launches and their summed
  * duration in milliseconds since the last reset (enable resets).  Kinds:
- * 0 = sample, 1 = trajectory, 2 = Fourier GEMM, 3 = spectrum reduction.
+ * 0 = sample, 1 = trajectory, 2 = Fourier GEMM, 3 = spectrum reduction,
+ * 4 = flow proposal (training and sampling).
  */
-#define SCIVR_KERNEL_KINDS 4
+#define SCIVR_KERNEL_KINDS 5
 scivr_status scivr_timing_enable(scivr_ctx *ctx, int32_t on);
 scivr_status scivr_kernel_times(scivr_ctx *ctx, int64_t *launches /*[SCIVR_KERNEL_KINDS]*/,
                                 double *ms /*[SCIVR_KERNEL_KINDS]*/);
+
+/* ---- learned importance-sampling proposal ----
+ *
+ * Not part of the paper's method: the paper draws initial conditions from
+ * the Husimi density of chi and weights trajectory j by 1/|<z_j|chi>|^2 =
+ * 1/((2 pi)^F rho_j) (section "Monte-Carlo SC-IVR algorithm", Eq. (11)).
+ * Any other sampling density keeps the estimator unbiased with the same
+ * weight formula, rho being that density; scivr_set_initial and
+ * scivr_flow_sample pass it as log_density.
+ *
+ * The proposal is an affine-coupling normalising flow over the whitened
+ * coordinates x = (xi, eta), xi_i = sqrt(gamma_i)(q_i - q_eq,i), eta_i =
+ * (p_i - p_eq,i)/sqrt(gamma_i), in which the Husimi density is N(0, I) and
+ * which have unit Jacobian.  n_layers coupling layers: layer l conditions on
+ * xi (l even) or eta (l odd) and maps the other half b to b exp(s) + t, with
+ * (s_raw, t) from a tanh MLP F -> width -> width -> 2F and s = 2 tanh(s_raw/2).
+ * Parameters (FP32, one flat array, per layer): W1 [width][F], b1 [width],
+ * W2 [width][width], b2 [width], W3 [2F][width], b3 [2F]; W3 rows 0..F-1
+ * give s_raw and F..2F-1 give t.
+ *
+ * A flow belongs to one context (it reads the context's problem and writes
+ * its initial conditions); destroy it before the context.
+ */
+typedef struct scivr_flow scivr_flow;
+
+/*
+ * New flow with W1, W2 entries N(0,1)/sqrt(fan-in) from Philox4x64-10 (key
+ * (seed, 0), counter (parameter index, 0, 2, 0)) and zero biases and output
+ * layer: the initial flow is the identity, its density the Husimi density.
+ * Errors: SCIVR_EINVAL (n_layers outside [1, 64], width outside [1, 1024]),
+ * SCIVR_ENOMEM, SCIVR_EDEVICE.  On error *out is NULL.
+ */
+scivr_status scivr_flow_create(scivr_ctx *ctx, int32_t n_layers, int32_t width, uint64_t seed, scivr_flow **out);
+
+/* Free the flow (synchronises its device first).  NULL is ignored. */
+void scivr_flow_destroy(scivr_flow *flow);
+
+/* Number of FP32 parameters (-1 for NULL). */
+int64_t scivr_flow_param_count(const scivr_flow *flow);
+
+/* Replace the parameters (count must equal the parameter count) and reset the Adam state. */
+scivr_status scivr_flow_set_params(scivr_flow *flow, const float *params, int64_t count, int32_t mem_kind,
+                                   void *stream);
+
+/* Synchronise and copy the parameters to host memory. */
+scivr_status scivr_flow_get_params(scivr_flow *flow, float *params, int64_t count);
+
+/*
+ * Weighted maximum likelihood: points (p0, q0 [F][n]) drawn from some
+ * density r, with contributions c[n] = w_j sum_k |A_jk|^2 (w_j = 1/((2 pi)^F
+ * r_j), as scivr_read_contributions returns them), are proportional to the
+ * ideal sampling density divided by r; minimise L = -sum c_j log q(x_j) /
+ * sum c_j with Adam (lr, beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected),
+ * in FP32, over contiguous mini-batches [b batch, (b+1) batch) of the data in
+ * order, `epochs` times; a mini-batch with sum c = 0 is skipped.  The Adam
+ * state carries over between calls.  mem_kind: host or device arrays.
+ * *last_loss (may be NULL) receives L of the last mini-batch.  Synchronises.
+ */
+scivr_status scivr_flow_train(scivr_flow *flow, int64_t n, const double *p0, const double *q0, const double *c,
+                              int32_t mem_kind, int32_t epochs, int32_t batch, float lr, void *stream,
+                              double *last_loss);
+
+/* As scivr_flow_train on the context's current batch: its initial conditions
+ * and the contributions of its last accumulate call (SCIVR_ESTATE if none). */
+scivr_status scivr_flow_train_on_batch(scivr_flow *flow, int32_t epochs, int32_t batch, float lr, void *stream,
+                                       double *last_loss);
+
+/* One full-batch evaluation of L and dL/dparams (FP32) without a step; loss
+ * and grad [param count] are host outputs, either may be NULL.  Synchronises. */
+scivr_status scivr_flow_loss_grad(scivr_flow *flow, int64_t n, const double *p0, const double *q0, const double *c,
+                                  int32_t mem_kind, double *loss, float *grad);
+
+/*
+ * log q(p0, q0) of the flow alone (FP32 networks, or BF16 matrix-core
+ * networks as the sampler uses when use_bf16 != 0): logq [n] and, if u is
+ * not NULL, the latent points u [n][2F] (FP32), both host outputs.
+ * Synchronises.
+ */
+scivr_status scivr_flow_log_density(scivr_flow *flow, int64_t n, const double *p0, const double *q0,
+                                    int32_t mem_kind, int32_t use_bf16, double *logq, float *u);
+
+/*
+ * Fill the context's initial conditions with n (<= max_traj) points of the
+ * defensive mixture alpha N + (1 - alpha) q: point j (global index g =
+ * first_index + j) draws its 2F normals exactly as scivr_sample_husimi does
+ * and one uniform from counter (g, 0, 1, 0); if the uniform is below alpha
+ * the point is those normals (the Husimi draw), otherwise their image under
+ * the flow (BF16 networks on the matrix cores, FP32 affine steps).
+ * log_density is ln(alpha N(x) + (1 - alpha) q(x)).  The effective sample size
+ * of the ratios N(x_j)/density(x_j), divided by n, goes to *ess_frac; if it
+ * is below min_ess_frac the batch is redrawn from the Husimi density with
+ * the same seed and indices and *used_flow is 0 (else 1).  alpha = 1 gives
+ * exactly scivr_sample_husimi.  Resets the propagation state.  Synchronises.
+ */
+scivr_status scivr_flow_sample(scivr_flow *flow, uint64_t seed, uint64_t first_index, int64_t n, double alpha,
+                               double min_ess_frac, double *ess_frac, int32_t *used_flow, void *stream);
 
 #ifdef __cplusplus
 }

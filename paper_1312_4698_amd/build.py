@@ -22,7 +22,9 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libscivr.so")
 ARCH = os.environ.get("SCIVR_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["api.hip", "traj.hip", "fourier_fp64.hip", "fourier_f16.hip", "aux_kernels.hip"]
+# largest first: the compile jobs run in parallel
+SOURCES = ["traj_big.hip", "traj.hip", "api.hip", "flow_api.hip", "fourier_fp64.hip", "fourier_f16.hip",
+           "aux_kernels.hip", "flow_kernels.hip"]
 
 HIPCC = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
 
@@ -44,7 +46,7 @@ def _compile(src: str) -> str:
 
 def build(verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
-    jobs = min(len(SOURCES), max(1, (os.cpu_count() or 2) // 2))
+    jobs = min(len(SOURCES), max(1, os.cpu_count() or 2))
     with concurrent.futures.ThreadPoolExecutor(jobs) as ex:
         objs = list(ex.map(_compile, SOURCES))
     tmp = LIB + ".tmp"

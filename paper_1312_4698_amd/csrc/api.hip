@@ -54,7 +54,8 @@ void free_all(scivr_ctx *c)
 {
     void *ptrs[] = {c->d_prob,   c->d_p0,        c->d_q0,           c->d_logrho,  c->d_p,     c->d_q,
                     c->d_scal,   c->d_M,         c->d_amp,          c->d_amp16,   c->d_phase, c->d_weight,
-                    c->d_part_spec, c->d_part_contrib, c->d_contrib, c->d_total, c->d_ngood};
+                    c->d_part_spec, c->d_part_contrib, c->d_contrib, c->d_total, c->d_ngood, c->d_goodw,
+                    c->d_goodw_row};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     for (auto &e : c->events) {
@@ -228,6 +229,8 @@ scivr_status scivr_create(const scivr_problem *p, int32_t device, scivr_ctx **ou
     A(dalloc(&c->d_contrib, NP));
     A(dalloc(&c->d_total, c->n_energies));
     A(dalloc(&c->d_ngood, 1));
+    A(dalloc(&c->d_goodw, 1));
+    A(dalloc(&c->d_goodw_row, NP));
     if (ea != hipSuccess) {
         const bool oom = (ea == hipErrorOutOfMemory || ea == hipErrorMemoryAllocation);
         free_all(c);
@@ -243,6 +246,7 @@ scivr_status scivr_create(const scivr_problem *p, int32_t device, scivr_ctx **ou
     if (e == hipSuccess) e = launch_fill_zero(c->d_scal, NSCAL * NP, s0);
     if (e == hipSuccess) e = launch_fill_zero(c->d_total, c->n_energies, s0);
     if (e == hipSuccess) e = launch_fill_zero((double *)c->d_ngood, 1, s0);
+    if (e == hipSuccess) e = launch_fill_zero(c->d_goodw, 1, s0);
     if (e == hipSuccess && !mixed)
         e = launch_phase_table(p->e_min, p->e_max, p->n_energies, c->kpad, c->nt, c->nt_alloc, p->dt, c->d_phase, s0);
     if (e == hipSuccess) e = hipDeviceSynchronize();
@@ -276,6 +280,7 @@ scivr_status scivr_sample_husimi(scivr_ctx *ctx, uint64_t seed, uint64_t first_i
     ctx->n_traj = n_traj;
     ctx->steps_done = 0;
     ctx->have_initial = true;
+    ctx->husimi_batch = true;
     ctx->accumulated = false;
     return SCIVR_OK;
 }
@@ -299,6 +304,7 @@ scivr_status scivr_set_initial(scivr_ctx *ctx, int64_t n_traj, const double *p0,
     ctx->n_traj = n_traj;
     ctx->steps_done = 0;
     ctx->have_initial = true;
+    ctx->husimi_batch = false;
     ctx->accumulated = false;
     return SCIVR_OK;
 }
@@ -345,9 +351,10 @@ scivr_status scivr_accumulate_spectrum(scivr_ctx *ctx, void *stream)
                     ctx->n_steps);
     if (ctx->accumulated) return ctx_fail(ctx, SCIVR_ESTATE, "batch already accumulated");
     hipStream_t s = (hipStream_t)stream;
-    HIPCALL(ctx, launch_weights(ctx->d_scal + SC_GOOD * ctx->npad, ctx->d_scal + SC_ESCALE * ctx->npad,
-                                ctx->d_logrho, ctx->host_prob.F_log_2pi, ctx->n_traj, ctx->npad, ctx->d_weight,
-                                ctx->d_ngood, s));
+    HIPCALL(ctx, launch_weights(ctx->d_prob, ctx->F, ctx->d_scal + SC_GOOD * ctx->npad,
+                                ctx->d_scal + SC_ESCALE * ctx->npad, ctx->d_logrho, ctx->d_p0, ctx->d_q0,
+                                ctx->husimi_batch, ctx->n_traj, ctx->npad, ctx->d_weight, ctx->d_goodw_row,
+                                ctx->d_ngood, ctx->d_goodw, s));
     // only the row tiles that hold trajectories of this batch
     const int32_t row_tiles = (int32_t)((ctx->n_traj + GEMM_BM - 1) / GEMM_BM);
     if (ctx->precision == SCIVR_PRECISION_MIXED) {
@@ -410,9 +417,11 @@ scivr_status scivr_read_spectrum(scivr_ctx *ctx, double *I_host, int64_t *n_good
         if (ng == 0) {
             for (int k = 0; k < ctx->n_energies; ++k) I_host[k] = 0.0;
         } else {
+            double gw = 0.0;
+            HIPCALL(ctx, hipMemcpy(&gw, ctx->d_goodw, sizeof gw, hipMemcpyDeviceToHost));
             HIPCALL(ctx, hipMemcpy(I_host, ctx->d_total, sizeof(double) * ctx->n_energies, hipMemcpyDeviceToHost));
             const double T = (double)ctx->n_steps * ctx->dt;
-            const double scale = ctx->dt * ctx->dt / (2.0 * M_PI * T * (double)ng);
+            const double scale = ctx->dt * ctx->dt / (2.0 * M_PI * T * gw);
             for (int k = 0; k < ctx->n_energies; ++k) I_host[k] *= scale;
         }
     }
@@ -425,6 +434,7 @@ scivr_status scivr_reset_spectrum(scivr_ctx *ctx, void *stream)
     hipStream_t s = (hipStream_t)stream;
     HIPCALL(ctx, launch_fill_zero(ctx->d_total, ctx->n_energies, s));
     HIPCALL(ctx, launch_fill_zero((double *)ctx->d_ngood, 1, s));
+    HIPCALL(ctx, launch_fill_zero(ctx->d_goodw, 1, s));
     ctx->n_total = 0;
     return SCIVR_OK;
 }

@@ -2,40 +2,11 @@
 // phase table, per-trajectory weights, deterministic reductions.
 #include <math.h>
 
+#include "philox.h"
 #include "scivr_internal.h"
 
 namespace scivr {
 namespace {
-
-// Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two 64x64->128
-// multiplications with key bumps by the golden-ratio and sqrt(3)-1 Weyl constants.
-__device__ inline void philox4x64_10(uint64_t c0, uint64_t c1, uint64_t c2, uint64_t c3, uint64_t k0, uint64_t k1,
-                                     uint64_t out[4])
-{
-    const uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
-    const uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
-#pragma unroll
-    for (int r = 0; r < 10; ++r) {
-        if (r > 0) {
-            k0 += W0;
-            k1 += W1;
-        }
-        const uint64_t hi0 = __umul64hi(M0, c0), lo0 = M0 * c0;
-        const uint64_t hi1 = __umul64hi(M1, c2), lo1 = M1 * c2;
-        const uint64_t n0 = hi1 ^ c1 ^ k0;
-        const uint64_t n2 = hi0 ^ c3 ^ k1;
-        c0 = n0;
-        c1 = lo1;
-        c2 = n2;
-        c3 = lo0;
-    }
-    out[0] = c0;
-    out[1] = c1;
-    out[2] = c2;
-    out[3] = c3;
-}
-
-__device__ inline double u01(uint64_t x) { return ((double)(x >> 11) + 0.5) * (1.0 / 9007199254740992.0); }
 
 // One thread per trajectory: 2F normals from ceil(2F/4) Philox blocks with
 // counter (index, block, 0, 0) and key (seed, 0), Box-Muller on uniform pairs;
@@ -46,7 +17,6 @@ __global__ void sample_husimi_kernel(const ProblemDev *__restrict__ P, int F, ui
 {
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= n) return;
-    const double two_pi = 6.283185307179586476925286766559;
     double sq = 0.0;
     const int count = 2 * F;
     for (int b = 0; 4 * b < count; ++b) {
@@ -56,10 +26,8 @@ __global__ void sample_husimi_kernel(const ProblemDev *__restrict__ P, int F, ui
         for (int h = 0; h < 2; ++h) {
             const int i0 = 4 * b + 2 * h;
             if (i0 >= count) break;
-            const double rad = sqrt(-2.0 * log(u01(r[2 * h])));
-            double s, co;
-            sincos(two_pi * u01(r[2 * h + 1]), &s, &co);
-            const double xi = rad * co, eta = rad * s;  // normals i0 and i0 + 1
+            double xi, eta;  // normals i0 and i0 + 1
+            box_muller(r[2 * h], r[2 * h + 1], xi, eta);
             const int mode = i0 / 2;
             q0[mode * npad + j] = P->q_eq[mode] + xi / P->sqrt_gamma[mode];
             p0[mode * npad + j] = P->p_eq[mode] + eta * P->sqrt_gamma[mode];
@@ -91,23 +59,52 @@ __global__ void phase_table_kernel(double e_min, double e_max, int K, int kpad, 
 
 // weight_j = good_j exp(-ln rho_j - F ln 2 pi) 4^-e_j for j < n, 0 in the padding
 // (e_j: the power-of-two scale the mixed form applied to trajectory j's
-// amplitudes, 0 in the FP64 form); counts good trajectories.
-__global__ void weights_kernel(const double *__restrict__ good_row, const double *__restrict__ escale_row,
-                               const double *__restrict__ logrho, double F_log_2pi, int64_t n, int64_t npad,
-                               double *weight, unsigned long long *n_good)
+// amplitudes, 0 in the FP64 form); counts good trajectories, and gives each
+// good trajectory its ratio r_j = Husimi density / sampling density (1 for a
+// Husimi batch), whose sum replaces n_good in the normalisation of Eq. (11).
+__global__ void weights_kernel(const ProblemDev *__restrict__ P, int F, const double *__restrict__ good_row,
+                               const double *__restrict__ escale_row, const double *__restrict__ logrho,
+                               const double *__restrict__ p0, const double *__restrict__ q0, int husimi, int64_t n,
+                               int64_t npad, double *weight, double *goodw_row, unsigned long long *n_good)
 {
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     bool g = false;
     if (j < npad) {
-        double w = 0.0;
+        double w = 0.0, r = 0.0;
         if (j < n && good_row[j] != 0.0) {
-            w = ldexp(exp(-logrho[j] - F_log_2pi), -2 * (int)escale_row[j]);
+            w = ldexp(exp(-logrho[j] - P->F_log_2pi), -2 * (int)escale_row[j]);
             g = true;
+            r = 1.0;
+            if (!husimi) {
+                double sq = 0.0;
+                for (int i = 0; i < F; ++i) {
+                    const double xi = (q0[i * npad + j] - P->q_eq[i]) * P->sqrt_gamma[i];
+                    const double eta = (p0[i * npad + j] - P->p_eq[i]) * P->inv_sqrt_gamma[i];
+                    sq += xi * xi + eta * eta;
+                }
+                r = exp(-P->F_log_2pi - 0.5 * sq - logrho[j]);
+            }
         }
         weight[j] = w;
+        goodw_row[j] = r;
     }
     const unsigned long long cnt = __popcll(__ballot(g));
     if ((threadIdx.x & 63) == 0 && cnt) atomicAdd(n_good, cnt);
+}
+
+// total += sum_j row[j] over j < n in a fixed order (one workgroup).
+__global__ void row_sum_kernel(const double *__restrict__ row, int64_t n, double *total)
+{
+    __shared__ double red[256];
+    double s = 0.0;
+    for (int64_t j = threadIdx.x; j < n; j += 256) s += row[j];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) total[0] += red[0];
 }
 
 // total[k] += sum over row tiles of part[rt][k], in row-tile order (deterministic).
@@ -160,11 +157,16 @@ hipError_t launch_phase_table(double e_min, double e_max, int K, int kpad, int n
     return hipGetLastError();
 }
 
-hipError_t launch_weights(const double *good_row, const double *escale_row, const double *logrho, double F_log_2pi,
-                          int64_t n, int64_t npad, double *weight, unsigned long long *n_good, hipStream_t s)
+hipError_t launch_weights(const ProblemDev *P, int F, const double *good_row, const double *escale_row,
+                          const double *logrho, const double *p0, const double *q0, bool husimi, int64_t n,
+                          int64_t npad, double *weight, double *goodw_row, unsigned long long *n_good,
+                          double *goodw_total, hipStream_t s)
 {
-    hipLaunchKernelGGL(weights_kernel, dim3(blocks_for(npad, 256)), dim3(256), 0, s, good_row, escale_row, logrho,
-                       F_log_2pi, n, npad, weight, n_good);
+    hipLaunchKernelGGL(weights_kernel, dim3(blocks_for(npad, 256)), dim3(256), 0, s, P, F, good_row, escale_row,
+                       logrho, p0, q0, husimi ? 1 : 0, n, npad, weight, goodw_row, n_good);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(row_sum_kernel, dim3(1), dim3(256), 0, s, goodw_row, n, goodw_total);
     return hipGetLastError();
 }
 

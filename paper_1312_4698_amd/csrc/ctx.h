@@ -33,6 +33,9 @@ struct scivr_ctx {
     double *d_weight = nullptr, *d_part_spec = nullptr, *d_part_contrib = nullptr, *d_contrib = nullptr;
     double *d_total = nullptr;
     unsigned long long *d_ngood = nullptr;
+    double *d_goodw = nullptr;      // running sum of good_j r_j (r_j = Husimi / sampling density)
+    double *d_goodw_row = nullptr;  // good_j r_j of the current batch [npad]
+    bool husimi_batch = false;      // the batch was drawn by the Husimi sampler (r_j = 1 exactly)
 
     int64_t n_traj = 0;      // current batch size
     int32_t steps_done = 0;

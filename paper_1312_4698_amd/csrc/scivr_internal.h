@@ -8,7 +8,7 @@
 
 namespace scivr {
 
-constexpr int FMAX = 16;
+constexpr int FMAX = 32;
 
 // Tile sizes of the Fourier GEMM: a workgroup covers GEMM_BM trajectories x
 // GEMM_BN energies; the time axis is consumed GEMM_BK samples per MFMA step.
@@ -76,12 +76,15 @@ struct GemmArgs {
 };
 
 hipError_t launch_traj(int F, bool mixed, const TrajArgs &a, hipStream_t s);
+hipError_t launch_traj_big(int F, bool mixed, const TrajArgs &a, hipStream_t s);  // 17 <= F <= 32
 hipError_t launch_sample_husimi(const ProblemDev *P, int F, uint64_t seed, uint64_t first, int64_t n, int64_t npad,
                                 double *p0, double *q0, double *logrho, hipStream_t s);
 hipError_t launch_phase_table(double e_min, double e_max, int K, int kpad, int nt, int nt_pad, double dt,
                               double2 *phase, hipStream_t s);
-hipError_t launch_weights(const double *good_row, const double *escale_row, const double *logrho, double F_log_2pi,
-                          int64_t n, int64_t npad, double *weight, unsigned long long *n_good, hipStream_t s);
+hipError_t launch_weights(const ProblemDev *P, int F, const double *good_row, const double *escale_row,
+                          const double *logrho, const double *p0, const double *q0, bool husimi, int64_t n,
+                          int64_t npad, double *weight, double *goodw_row, unsigned long long *n_good,
+                          double *goodw_total, hipStream_t s);
 hipError_t launch_fourier_fp64(const GemmArgs &a, hipStream_t s);
 hipError_t launch_fourier_f16(const GemmF16Args &a, hipStream_t s);
 hipError_t launch_spectrum_reduce(const double *part_spec, int row_tiles, int K, int kpad, double *total,

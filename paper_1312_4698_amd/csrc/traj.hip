@@ -34,6 +34,7 @@
 #include <type_traits>
 
 #include "scivr_internal.h"
+#include "traj_common.h"
 
 namespace scivr {
 namespace {
@@ -48,35 +49,6 @@ struct alignas(16) GroupLds {
     unsigned long long slotM[N2];      // per-step argmax keys of the two eliminations
     unsigned long long slotA[F + (F & 1)];
 };
-
-__device__ inline unsigned long long dbits(double x) { return (unsigned long long)__double_as_longlong(x); }
-
-// Workgroups are one wave, and a wave's LDS instructions execute in issue
-// order, so a write by one lane is visible to a later read by another lane of
-// the same wave without waiting; only the compiler must keep the order.
-__device__ inline void lds_order()
-{
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-}
-
-typedef const __attribute__((address_space(4))) ProblemDev *ConstProblem;
-
-// A fresh, opaque handle to the trajectory-independent constants.  Taking it
-// inside the time loop keeps their uniform doubles as scalar-cache loads there
-// instead of letting them be hoisted into (and spilled out of) the scalar
-// register file.
-__device__ inline ConstProblem opaque(const ProblemDev *P)
-{
-    uint64_t v = (uint64_t)P;
-    asm volatile("" : "+s"(v));
-    return (ConstProblem)v;
-}
-
-__device__ inline unsigned long long pivot_key(double mag, int pos)
-{
-    return (dbits(mag) & ~63ull) | (unsigned long long)(63 - pos);
-}
 
 // det of the real N x N matrix (N = 2F) whose rows at positions pos0, pos1
 // live in lane-local a0[], a1[].  Each step: LDS atomic max over packed
@@ -188,51 +160,6 @@ __device__ inline void lu_det_complex(double (&ar)[N], double (&ai)[N], int pos,
 // Waves per SIMD the register allocator must allow (unified 512-register file).
 template <int F>
 constexpr int traj_waves() { return F <= 3 ? 4 : (F <= 6 ? 3 : (F <= 12 ? 2 : 1)); }
-
-// Kahan-compensated running sum (used for the FP32 action of the mixed form).
-struct Kahan {
-    float s = 0.f, c = 0.f;
-    __device__ void add(float x)
-    {
-        const float y = x - c;
-        const float t = s + y;
-        c = (t - s) - y;
-        s = t;
-    }
-    __device__ double value() const { return (double)s - (double)c; }
-};
-
-template <bool MIXED>
-struct Action;
-template <>
-struct Action<false> {
-    double s = 0.0;
-    __device__ void add(double x) { s += x; }
-    __device__ double value() const { return s; }
-    __device__ void load(double v, double) { s = v; }
-    __device__ double hi() const { return s; }
-    __device__ double lo() const { return 0.0; }
-};
-template <>
-struct Action<true> {
-    Kahan k;
-    __device__ void add(double x) { k.add((float)x); }
-    __device__ double value() const { return k.value(); }
-    __device__ void load(double v, double comp)
-    {
-        k.s = (float)v;
-        k.c = (float)comp;
-    }
-    __device__ double hi() const { return (double)k.s; }
-    __device__ double lo() const { return (double)k.c; }
-};
-
-// Split x into FP16 hi + lo with x ~ hi + lo to about 22 bits.
-__device__ inline void split_f16(float x, _Float16 &hi, _Float16 &lo)
-{
-    hi = (_Float16)x;
-    lo = (_Float16)(x - (float)hi);
-}
 
 // The trajectory kernel.  MIXED = false: every trajectory quantity in FP64.
 // MIXED = true: the trajectory (p, q), the potential, gradient and Hessian
@@ -584,6 +511,7 @@ hipError_t launch_any(int F, const TrajArgs &a, hipStream_t s)
 
 hipError_t launch_traj(int F, bool mixed, const TrajArgs &a, hipStream_t s)
 {
+    if (F > 16) return launch_traj_big(F, mixed, a, s);
     return mixed ? launch_any<true>(F, a, s) : launch_any<false>(F, a, s);
 }
 

@@ -1,0 +1,462 @@
+// Trajectory kernel of the TA-SC-IVR spectrum for large F (17 <= F <= 32):
+// one wave64 per trajectory.
+//
+// Lane c < 2F owns column c of the 2F x 2F monodromy matrix M = d(p_t, q_t) /
+// d(p_0, q_0) (the tangent vector of initial direction c, its p half dp[] and
+// q half dq[]); lane i < F also owns mode i of the trajectory (p_i, q_i and the
+// Morse terms of that mode), shared with the wave through LDS.  Per step:
+//  * the fourth-order symplectic triple jump (Yoshida / Forest-Ruth drifts
+//    and kicks), each kick applying the Hessian to the lane's tangent column
+//    in factored form H dq = h o dq + 4 q o (Lambda (q o dq)) with the coupling
+//    matrix Lambda as scalar operands;
+//  * M is written to LDS column by column and read back row by row (odd row
+//    stride, so both directions are free of bank conflicts), and each lane
+//    reloads its column afterwards (so the register copy is dead while the
+//    eliminations run): lane i < F forms
+//    row i of the Herman-Kluk prefactor matrix A of Eq. (5) from rows i and
+//    F + i, and lane r < 2F takes row r of M; det(A) (complex) and det(M)
+//    (real, the stability monitor after Eq. (5)) follow by Gaussian
+//    elimination with partial pivoting across the lanes, one row per lane,
+//    exactly as in the small-F kernel (LDS atomic max over packed (|a|,
+//    position) keys picks each pivot, the pivot lane publishes its row);
+//  * lane 0 keeps the action, the continuous prefactor phase and writes the
+//    amplitude of the time sample.
+// The state layout, the branch tracking and the amplitude storage (FP64
+// time-major, or FP16 hi/lo planes in the mixed form) are the small-F
+// kernel's.
+#include <math.h>
+
+#include <type_traits>
+
+#include "scivr_internal.h"
+#include "traj_common.h"
+
+namespace scivr {
+namespace {
+
+template <int F>
+struct alignas(16) BigLds {
+    static constexpr int N2 = 2 * F;
+    static constexpr int RS = N2 + 1;  // odd row stride of the transpose buffer
+    double T[N2 * RS];                 // M, row r at T + r RS
+    double lam[F * F];                 // coupling matrix, row-major, zero diagonal
+    double piv[N2];                    // pivot row (complex elimination: re, im interleaved)
+    unsigned long long slot[N2];       // per-column argmax keys
+};
+
+// det of the real N x N matrix whose row `pos` lives in a[] of the lanes with
+// `active` set (positions 0..N-1, one row per lane).  Every lane returns det.
+template <int N>
+__device__ inline double lu_det_rows(double (&a)[N], bool active, int pos, double *piv, unsigned long long *slot)
+{
+    bool alive = active;
+    if (active) slot[pos] = 0ull;
+    double det = 1.0;
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+        lds_order();
+        if (alive) atomicMax(&slot[k], pivot_key(fabs(a[k]), pos));
+        lds_order();
+        const unsigned long long win = __hip_atomic_load(&slot[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+        const int ppos = 63 - (int)(win & 63ull);
+        const bool isp = alive && pos == ppos;
+        if (isp) {
+#pragma unroll
+            for (int jj = k; jj < N; ++jj) piv[jj] = a[jj];
+        }
+        lds_order();
+        const double pk = piv[k];
+        det *= (ppos != k) ? -pk : pk;
+        pos = (alive && pos == k) ? ppos : pos;
+        alive = alive && !isp;
+        if (alive) {
+            const double l = a[k] * rcp_nr(pk);
+#pragma unroll
+            for (int jj = k + 1; jj < N; ++jj) a[jj] = fma(-l, piv[jj], a[jj]);
+        }
+    }
+    lds_order();
+    return det;
+}
+
+// det of the complex N x N matrix whose row `pos` lives in (ar, ai) of the
+// active lanes; pivot on |a_k|^2.  Every lane returns (dr, di).
+template <int N>
+__device__ inline void lu_det_rows_complex(double (&ar)[N], double (&ai)[N], bool active, int pos, double *piv,
+                                           unsigned long long *slot, double &dr, double &di)
+{
+    bool alive = active;
+    if (active) slot[pos] = 0ull;
+    double zr = 1.0, zi = 0.0;
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+        const double m2 = fma(ar[k], ar[k], ai[k] * ai[k]);
+        lds_order();
+        if (alive) atomicMax(&slot[k], pivot_key(m2, pos));
+        lds_order();
+        const unsigned long long win = __hip_atomic_load(&slot[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+        const int ppos = 63 - (int)(win & 63ull);
+        const bool isp = alive && pos == ppos;
+        if (isp) {
+#pragma unroll
+            for (int jj = k; jj < N; ++jj) {
+                piv[2 * jj] = ar[jj];
+                piv[2 * jj + 1] = ai[jj];
+            }
+        }
+        lds_order();
+        const double pr = piv[2 * k], pi = piv[2 * k + 1];
+        const double nr = zr * pr - zi * pi;
+        const double ni = zr * pi + zi * pr;
+        zr = (ppos != k) ? -nr : nr;
+        zi = (ppos != k) ? -ni : ni;
+        pos = (alive && pos == k) ? ppos : pos;
+        alive = alive && !isp;
+        if (alive) {
+            const double inv = rcp_nr(fma(pr, pr, pi * pi));
+            const double lr = (ar[k] * pr + ai[k] * pi) * inv;
+            const double li = (ai[k] * pr - ar[k] * pi) * inv;
+#pragma unroll
+            for (int jj = k + 1; jj < N; ++jj) {
+                const double br = piv[2 * jj], bi = piv[2 * jj + 1];
+                ar[jj] = ar[jj] - (lr * br - li * bi);
+                ai[jj] = ai[jj] - (lr * bi + li * br);
+            }
+        }
+    }
+    lds_order();
+    dr = zr;
+    di = zi;
+}
+
+template <int F, bool MIXED>
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 1)))
+traj_big_kernel(TrajArgs A, const ProblemDev *__restrict__ P0)
+{
+    typedef typename std::conditional<MIXED, float, double>::type R;
+    constexpr int N2 = 2 * F;
+    constexpr int RS = BigLds<F>::RS;
+    constexpr int FP = F + (F & 1);
+    __shared__ BigLds<F> L;
+    __shared__ R qv[FP], pm[FP], phd[FP], pv[FP];
+
+    const int lane = threadIdx.x;
+    const ProblemDev *__restrict__ P = P0;
+    for (int idx = lane; idx < F * F; idx += 64) L.lam[idx] = P->lam[(idx / F) * FMAX + idx % F];
+    const int64_t jr = blockIdx.x;  // one trajectory per workgroup, grid = batch size
+    const int64_t NP = A.npad;
+    const bool colLane = lane < N2;
+    const bool modeLane = lane < F;
+    const int cm = modeLane ? lane : 0;
+
+    const R kc = (R)P->k[cm], Dc = (R)P->D[cm], ac = (R)P->a[cm];
+
+    double dp[F], dq[F];  // column `lane` of M: p rows and q rows
+    R pc = 0, qc = 0;     // mode `lane` of the trajectory (lanes < F)
+    Action<MIXED> S;
+    double theta, prev_r, prev_i, phi, detM, maxdev;
+    int escale = 0;
+    bool good;
+    if (A.step_begin == 0) {
+#pragma unroll
+        for (int i = 0; i < F; ++i) {
+            dp[i] = (lane == i) ? 1.0 : 0.0;
+            dq[i] = (lane == F + i) ? 1.0 : 0.0;
+        }
+        if (modeLane) {
+            pc = (R)A.p0[lane * NP + jr];
+            qc = (R)A.q0[lane * NP + jr];
+        }
+        theta = phi = prev_i = 0.0;
+        prev_r = 1.0;
+        detM = 1.0;
+        maxdev = 0.0;
+        good = true;
+    } else {
+        const int cc = colLane ? lane : 0;
+#pragma unroll
+        for (int i = 0; i < F; ++i) {
+            dp[i] = colLane ? A.Mst[(int64_t)(i * N2 + cc) * NP + jr] : 0.0;
+            dq[i] = colLane ? A.Mst[(int64_t)((F + i) * N2 + cc) * NP + jr] : 0.0;
+        }
+        if (modeLane) {
+            pc = (R)A.p[lane * NP + jr];
+            qc = (R)A.q[lane * NP + jr];
+        }
+        S.load(A.scal[SC_S * NP + jr], A.scal[SC_SCOMP * NP + jr]);
+        theta = A.scal[SC_THETA * NP + jr];
+        prev_r = A.scal[SC_PREV_RE * NP + jr];
+        prev_i = A.scal[SC_PREV_IM * NP + jr];
+        phi = A.scal[SC_PHI * NP + jr];
+        good = A.scal[SC_GOOD * NP + jr] != 0.0;
+        detM = A.scal[SC_DETM * NP + jr];
+        maxdev = A.scal[SC_MAXDEV * NP + jr];
+        escale = (int)A.scal[SC_ESCALE * NP + jr];
+    }
+    if (modeLane) {
+        qv[lane] = qc;
+        pm[lane] = pc;
+    }
+    lds_order();
+
+    // exponent and phase of <chi|p,q> of the published state
+    auto overlap = [&](auto PP, double &ph) -> double {
+        double ex = 0.0;
+        ph = 0.0;
+#pragma unroll
+        for (int i = 0; i < F; ++i) {
+            const double qi = (double)qv[i], pi = (double)pm[i];
+            const double dqe = PP->q_eq[i] - qi;
+            const double dpe = PP->p_eq[i] - pi;
+            ex += -0.25 * PP->gamma[i] * dqe * dqe - dpe * dpe * PP->inv4gamma[i];
+            ph += 0.5 * dqe * (PP->p_eq[i] + pi);
+        }
+        return ex;
+    };
+    auto store_amplitude = [&](auto PP, int t) {
+        double ph;
+        const double ex = overlap(PP, ph);
+        double s, co;
+        dsincos(ph + S.value() + phi, &PP->mc, &s, &co);
+        if constexpr (!MIXED) {
+            const double mag = dexp(ex, &PP->mc);
+            double2 r;
+            r.x = good ? mag * co : 0.0;
+            r.y = good ? mag * s : 0.0;
+            A.amp[(int64_t)t * NP + jr] = r;
+        } else {
+            const double mag = ldexp(dexp(ex, &PP->mc), escale);
+            const float re = good ? (float)(mag * co) : 0.f, im = good ? (float)(mag * s) : 0.f;
+            _Float16 h[4];
+            split_f16(re, h[0], h[1]);
+            split_f16(im, h[2], h[3]);
+            const int64_t e = ((int64_t)(t >> 3) * NP + jr) * 8 + (t & 7);
+#pragma unroll
+            for (int pl = 0; pl < 4; ++pl) A.amp16[pl * A.plane + e] = h[pl];
+        }
+    };
+
+    if (A.step_begin == 0 && lane == 0) {
+        if constexpr (MIXED) {
+            double ph;
+            const double ex0 = overlap(P, ph);
+            escale = (int)fmin(fmax(floor(-ex0 * 1.4426950408889634), 0.0), 12.0);
+        }
+        store_amplitude(P, 0);
+    }
+
+    for (int step = A.step_begin; step < A.step_end; ++step) {
+        ConstProblem Ps = opaque(P0);
+#pragma unroll 1
+        for (int s = 0; s < 4; ++s) {
+            ConstProblem Pk = opaque(P0);
+            // ---- drift ----
+            const double h = Pk->hd[s];
+            if (lane == 0) {
+                R kin = 0;
+#pragma unroll
+                for (int i = 0; i < F; ++i) {
+                    const R pi = pm[i];
+                    kin += (R)0.5 * pi * pi;
+                }
+                S.add(h * (double)kin);
+            }
+            if (modeLane) qc = fma((R)h, pc, qc);
+#pragma unroll
+            for (int i = 0; i < F; ++i) dq[i] = fma(h, dp[i], dq[i]);
+            lds_order();
+            if (modeLane) qv[lane] = qc;
+            lds_order();
+            if (s == 3) break;
+            // ---- kick: mode terms on lanes < F, shared through LDS ----
+            const double hk = Pk->hc[s];
+            if (modeLane) {
+                R sm = 0;
+#pragma unroll
+                for (int i = 0; i < F; ++i) {
+                    const R qi = qv[i];
+                    sm = fma((R)L.lam[lane * F + i], qi * qi, sm);
+                }
+                R e;
+                if constexpr (MIXED)
+                    e = expf(-ac * qc);
+                else
+                    e = dexp(-ac * qc, &Pk->mc);
+                const R one_e = (R)1 - e;
+                const R gc = kc * qc + (R)2 * Dc * ac * e * one_e + (R)2 * qc * sm;
+                const R hc = kc + (R)2 * Dc * ac * ac * e * ((R)2 * e - (R)1) + (R)2 * sm;
+                const R vc = (R)0.5 * kc * qc * qc + Dc * one_e * one_e + (R)0.5 * qc * qc * sm;
+                pc = fma(-(R)hk, gc, pc);
+                phd[lane] = hc;
+                pv[lane] = vc;
+                pm[lane] = pc;
+            }
+            lds_order();
+            if (lane == 0) {
+                R V = 0;
+#pragma unroll
+                for (int i = 0; i < F; ++i) V += pv[i];
+                S.add(-hk * (double)V);
+            }
+            // tangent kick of column `lane`: dp -= hk (h o dq + 4 q o Lambda (q o dq))
+            if (colLane) {
+                double u[F];
+#pragma unroll
+                for (int i = 0; i < F; ++i) u[i] = (double)qv[i] * dq[i];
+#pragma unroll
+                for (int i = 0; i < F; ++i) {
+                    double w0 = 0.0, w1 = 0.0;
+#pragma unroll
+                    for (int jj = 0; jj < F; ++jj) {
+                        if (jj == i) continue;
+                        const double l = Pk->lam[i * FMAX + jj];
+                        if (jj & 1)
+                            w1 = fma(l, u[jj], w1);
+                        else
+                            w0 = fma(l, u[jj], w0);
+                    }
+                    const double qi = (double)qv[i];
+                    dp[i] = fma(-hk, fma((double)phd[i], dq[i], 4.0 * qi * (w0 + w1)), dp[i]);
+                }
+            }
+            lds_order();
+        }
+
+        const int stp = step + 1;
+        const double t = (double)stp * Ps->dt;
+
+        // ---- M to LDS, column `lane` ----
+        if (colLane) {
+#pragma unroll
+            for (int i = 0; i < F; ++i) {
+                L.T[i * RS + lane] = dp[i];
+                L.T[(F + i) * RS + lane] = dq[i];
+            }
+        }
+        lds_order();
+
+        // prefactor matrix row `lane` (< F) from rows lane (Mpp, Mpq) and F + lane (Mqp, Mqq); det(A)
+        double dAr, dAi;
+        {
+            const double sgc = Ps->sqrt_gamma[cm], isgc = Ps->inv_sqrt_gamma[cm];
+            const double *r0 = L.T + cm * RS, *r1 = L.T + (F + cm) * RS;
+            double are[F], aim[F];
+#pragma unroll
+            for (int jj = 0; jj < F; ++jj) {
+                const double sj = Ps->sqrt_gamma[jj], isj = Ps->inv_sqrt_gamma[jj];
+                are[jj] = 0.5 * (sgc * r1[F + jj] * isj + r0[jj] * sj * isgc);
+                aim[jj] = 0.5 * (-sgc * r1[jj] * sj + r0[F + jj] * isgc * isj);
+            }
+            lu_det_rows_complex<F>(are, aim, modeLane, lane, L.piv, L.slot, dAr, dAi);
+        }
+
+        // stability monitor |det(M)^2 - 1| on checked steps, row `lane` (< 2F) of M per lane
+        const bool checked = (A.check_every <= 1) || (stp % A.check_every == 0) || (stp == A.n_steps);
+        if (checked) {
+            double a[N2];
+            const double *row = L.T + (colLane ? lane : 0) * RS;
+#pragma unroll
+            for (int jj = 0; jj < N2; ++jj) a[jj] = row[jj];
+            const double dM = lu_det_rows<N2>(a, colLane, lane, L.piv, L.slot);
+            const double dev = fabs(dM * dM - 1.0);
+            detM = dM;
+            if (!(dev <= maxdev)) maxdev = dev;
+            if (!(dev <= Ps->det_tol)) good = false;
+        }
+
+        // column `lane` back from LDS: the copy in registers is dead across the
+        // two eliminations, which keeps them within the register file
+        {
+            const int cc = colLane ? lane : 0;
+#pragma unroll
+            for (int i = 0; i < F; ++i) {
+                dp[i] = colLane ? L.T[i * RS + cc] : 0.0;
+                dq[i] = colLane ? L.T[(F + i) * RS + cc] : 0.0;
+            }
+        }
+
+        // continuous branch of the prefactor phase, as in the small-F kernel
+        if (lane == 0) {
+            int ex;
+            (void)frexp(fmax(fabs(dAr), fabs(dAi)), &ex);
+            dAr = ldexp(dAr, -ex);
+            dAi = ldexp(dAi, -ex);
+            const double ur = dAr * prev_r + dAi * prev_i;
+            const double ui = dAi * prev_r - dAr * prev_i;
+            const double zr = ur * Ps->cos_gdt - ui * Ps->sin_gdt;
+            const double zi = ur * Ps->sin_gdt + ui * Ps->cos_gdt;
+            theta += datan2(zi, zr, &Ps->mc);
+            prev_r = dAr;
+            prev_i = dAi;
+            phi = 0.5 * (theta - Ps->sum_gamma * t);
+            if (!isfinite(phi) || !isfinite(S.value())) good = false;
+            store_amplitude(Ps, stp);
+        }
+    }
+
+    // ---- save the state ----
+    if (modeLane) {
+        A.p[lane * NP + jr] = (double)pc;
+        A.q[lane * NP + jr] = (double)qc;
+    }
+    if (lane == 0) {
+        A.scal[SC_S * NP + jr] = S.hi();
+        A.scal[SC_SCOMP * NP + jr] = S.lo();
+        A.scal[SC_THETA * NP + jr] = theta;
+        A.scal[SC_PREV_RE * NP + jr] = prev_r;
+        A.scal[SC_PREV_IM * NP + jr] = prev_i;
+        A.scal[SC_PHI * NP + jr] = phi;
+        A.scal[SC_GOOD * NP + jr] = good ? 1.0 : 0.0;
+        A.scal[SC_DETM * NP + jr] = detM;
+        A.scal[SC_MAXDEV * NP + jr] = maxdev;
+        A.scal[SC_ESCALE * NP + jr] = (double)escale;
+    }
+    if (colLane) {
+#pragma unroll
+        for (int i = 0; i < F; ++i) {
+            A.Mst[(int64_t)(i * N2 + lane) * NP + jr] = dp[i];
+            A.Mst[(int64_t)((F + i) * N2 + lane) * NP + jr] = dq[i];
+        }
+    }
+}
+
+template <int F, bool MIXED>
+hipError_t launch_big_F(const TrajArgs &a, hipStream_t s)
+{
+    if (a.n <= 0) return hipSuccess;
+    hipLaunchKernelGGL((traj_big_kernel<F, MIXED>), dim3((unsigned)a.n), dim3(64), 0, s, a, a.prob);
+    return hipGetLastError();
+}
+
+template <bool MIXED>
+hipError_t launch_big_any(int F, const TrajArgs &a, hipStream_t s)
+{
+    switch (F) {
+    case 17: return launch_big_F<17, MIXED>(a, s);
+    case 18: return launch_big_F<18, MIXED>(a, s);
+    case 19: return launch_big_F<19, MIXED>(a, s);
+    case 20: return launch_big_F<20, MIXED>(a, s);
+    case 21: return launch_big_F<21, MIXED>(a, s);
+    case 22: return launch_big_F<22, MIXED>(a, s);
+    case 23: return launch_big_F<23, MIXED>(a, s);
+    case 24: return launch_big_F<24, MIXED>(a, s);
+    case 25: return launch_big_F<25, MIXED>(a, s);
+    case 26: return launch_big_F<26, MIXED>(a, s);
+    case 27: return launch_big_F<27, MIXED>(a, s);
+    case 28: return launch_big_F<28, MIXED>(a, s);
+    case 29: return launch_big_F<29, MIXED>(a, s);
+    case 30: return launch_big_F<30, MIXED>(a, s);
+    case 31: return launch_big_F<31, MIXED>(a, s);
+    case 32: return launch_big_F<32, MIXED>(a, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_traj_big(int F, bool mixed, const TrajArgs &a, hipStream_t s)
+{
+    return mixed ? launch_big_any<true>(F, a, s) : launch_big_any<false>(F, a, s);
+}
+
+}  // namespace scivr

@@ -24,8 +24,8 @@ LIB_PATH = os.path.join(_HERE, "libscivr.so")
 
 OK, EINVAL, ENOMEM, EDEVICE, ESTATE, ENOGOOD, EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
 MEM_HOST, MEM_DEVICE = 0, 1
-KERNEL_KINDS = ("sample", "trajectory", "fourier", "reduce")
-F_MAX = 16
+KERNEL_KINDS = ("sample", "trajectory", "fourier", "reduce", "flow")
+F_MAX = 32
 
 _STATUS = {EINVAL: "SCIVR_EINVAL", ENOMEM: "SCIVR_ENOMEM", EDEVICE: "SCIVR_EDEVICE", ESTATE: "SCIVR_ESTATE",
            ENOGOOD: "SCIVR_ENOGOOD", EUNSUPPORTED: "SCIVR_EUNSUPPORTED"}
@@ -36,6 +36,9 @@ EXPORTED = (
     "scivr_set_initial", "scivr_propagate", "scivr_accumulate_spectrum", "scivr_read_spectrum",
     "scivr_reset_spectrum", "scivr_batch_info", "scivr_read_initial", "scivr_read_state",
     "scivr_read_amplitudes", "scivr_read_contributions", "scivr_timing_enable", "scivr_kernel_times",
+    "scivr_flow_create", "scivr_flow_destroy", "scivr_flow_param_count", "scivr_flow_set_params",
+    "scivr_flow_get_params", "scivr_flow_train", "scivr_flow_train_on_batch", "scivr_flow_loss_grad",
+    "scivr_flow_log_density", "scivr_flow_sample",
 )
 
 
@@ -98,6 +101,16 @@ def load() -> ctypes.CDLL:
         "scivr_read_contributions": (i32, [v, v]),
         "scivr_timing_enable": (i32, [v, i32]),
         "scivr_kernel_times": (i32, [v, v, v]),
+        "scivr_flow_create": (i32, [v, i32, i32, u64, ctypes.POINTER(v)]),
+        "scivr_flow_destroy": (None, [v]),
+        "scivr_flow_param_count": (i64, [v]),
+        "scivr_flow_set_params": (i32, [v, v, i64, i32, v]),
+        "scivr_flow_get_params": (i32, [v, v, i64]),
+        "scivr_flow_train": (i32, [v, i64, v, v, v, i32, i32, i32, ctypes.c_float, v, ctypes.POINTER(d)]),
+        "scivr_flow_train_on_batch": (i32, [v, i32, i32, ctypes.c_float, v, ctypes.POINTER(d)]),
+        "scivr_flow_loss_grad": (i32, [v, i64, v, v, v, i32, ctypes.POINTER(d), v]),
+        "scivr_flow_log_density": (i32, [v, i64, v, v, i32, i32, v, v]),
+        "scivr_flow_sample": (i32, [v, u64, u64, i64, d, d, ctypes.POINTER(d), ctypes.POINTER(i32), v]),
     }
     for name, (res, args) in sigs.items():
         f = getattr(lib, name)
@@ -271,6 +284,95 @@ class Context:
         ms = np.zeros(len(KERNEL_KINDS))
         self._check(self._lib.scivr_kernel_times(self._h, _np_ptr(cnt), _np_ptr(ms)))
         return {k: (int(cnt[i]), float(ms[i])) for i, k in enumerate(KERNEL_KINDS)}
+
+
+class Flow:
+    """Learned importance-sampling proposal bound to one context (``scivr_flow``)."""
+
+    def __init__(self, ctx: Context, n_layers: int = 4, width: int = 128, seed: int = 0):
+        self.ctx = ctx
+        self._lib = ctx._lib
+        h = ctypes.c_void_p()
+        st = self._lib.scivr_flow_create(ctx._h, int(n_layers), int(width), int(seed), ctypes.byref(h))
+        if st != OK:
+            raise ScivrError(st, self._lib.scivr_last_error(ctx._h).decode())
+        self._h = h
+        self.n_layers, self.width = int(n_layers), int(width)
+        self.n_params = int(self._lib.scivr_flow_param_count(h))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.scivr_flow_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st: int):
+        return self.ctx._check(st)
+
+    @staticmethod
+    def _points(p0, q0, c=None):
+        p0 = np.ascontiguousarray(p0, dtype=np.float64)
+        q0 = np.ascontiguousarray(q0, dtype=np.float64)
+        assert p0.shape == q0.shape and p0.ndim == 2
+        cc = None if c is None else np.ascontiguousarray(c, dtype=np.float64)
+        return p0, q0, cc
+
+    def set_params(self, params: np.ndarray):
+        a = np.ascontiguousarray(params, dtype=np.float32)
+        assert a.size == self.n_params
+        self._check(self._lib.scivr_flow_set_params(self._h, _np_ptr(a), a.size, MEM_HOST, None))
+
+    def get_params(self) -> np.ndarray:
+        a = np.zeros(self.n_params, dtype=np.float32)
+        self._check(self._lib.scivr_flow_get_params(self._h, _np_ptr(a), a.size))
+        return a
+
+    def train(self, p0, q0, c, epochs: int, batch: int, lr: float, stream=None) -> float:
+        p0, q0, c = self._points(p0, q0, c)
+        loss = ctypes.c_double()
+        self._check(self._lib.scivr_flow_train(self._h, p0.shape[1], _np_ptr(p0), _np_ptr(q0), _np_ptr(c), MEM_HOST,
+                                               int(epochs), int(batch), float(lr), _stream(stream),
+                                               ctypes.byref(loss)))
+        return float(loss.value)
+
+    def train_on_batch(self, epochs: int, batch: int, lr: float, stream=None) -> float:
+        loss = ctypes.c_double()
+        self._check(self._lib.scivr_flow_train_on_batch(self._h, int(epochs), int(batch), float(lr), _stream(stream),
+                                                        ctypes.byref(loss)))
+        return float(loss.value)
+
+    def loss_grad(self, p0, q0, c):
+        p0, q0, c = self._points(p0, q0, c)
+        loss = ctypes.c_double()
+        g = np.zeros(self.n_params, dtype=np.float32)
+        self._check(self._lib.scivr_flow_loss_grad(self._h, p0.shape[1], _np_ptr(p0), _np_ptr(q0), _np_ptr(c),
+                                                   MEM_HOST, ctypes.byref(loss), _np_ptr(g)))
+        return float(loss.value), g
+
+    def log_density(self, p0, q0, bf16: bool = False):
+        """(log q [n], u [n][2F]) of the flow alone."""
+        p0, q0, _ = self._points(p0, q0)
+        n = p0.shape[1]
+        lq = np.zeros(n)
+        u = np.zeros((n, 2 * self.ctx.F), dtype=np.float32)
+        self._check(self._lib.scivr_flow_log_density(self._h, n, _np_ptr(p0), _np_ptr(q0), MEM_HOST,
+                                                     1 if bf16 else 0, _np_ptr(lq), _np_ptr(u)))
+        return lq, u
+
+    def sample(self, seed: int, n_traj: int, first_index: int = 0, alpha: float = 0.1, min_ess_frac: float = 0.1,
+               stream=None):
+        """Fill the context's batch from the mixture; returns (ess_frac, used_flow)."""
+        ess = ctypes.c_double()
+        used = ctypes.c_int32()
+        self._check(self._lib.scivr_flow_sample(self._h, int(seed), int(first_index), int(n_traj), float(alpha),
+                                                float(min_ess_frac), ctypes.byref(ess), ctypes.byref(used),
+                                                _stream(stream)))
+        return float(ess.value), bool(used.value)
 
 
 def abi_version() -> int:

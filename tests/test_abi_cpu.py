@@ -28,7 +28,7 @@ def test_header_declarations_are_all_exported():
     assert declared, "no declarations parsed"
     assert declared <= exported, declared - exported
     assert declared == set(S.EXPORTED)
-    assert S.abi_version() == 1
+    assert S.abi_version() == 2
 
 
 def _create(S, lib, prob, max_traj=16):
@@ -52,7 +52,7 @@ def _create(S, lib, prob, max_traj=16):
 
 
 @pytest.mark.parametrize("field,value", [
-    ("F", 0), ("F", 17), ("n_steps", 0), ("n_energies", 1), ("e_max", -1.0), ("dt", 0.0), ("dt", float("nan")),
+    ("F", 0), ("F", 33), ("n_steps", 0), ("n_energies", 1), ("e_max", -1.0), ("dt", 0.0), ("dt", float("nan")),
     ("check_every", 0), ("det_tol", -1.0), ("precision", 7),
 ])
 def test_create_rejects_invalid_problems(field, value):
@@ -92,3 +92,19 @@ def test_null_arguments_are_rejected():
     assert lib.scivr_read_spectrum(None, None, None, None) == S.EINVAL
     lib.scivr_destroy(None)
     assert lib.scivr_last_error(None) == b"null context"
+
+
+def test_flow_entry_points_reject_null_without_a_device():
+    S, lib = _lib()
+    h = ctypes.c_void_p(12345)
+    assert lib.scivr_flow_create(None, 4, 128, 0, ctypes.byref(h)) == S.EINVAL
+    assert lib.scivr_flow_param_count(None) == -1
+    lib.scivr_flow_destroy(None)
+    d = ctypes.c_double()
+    assert lib.scivr_flow_train(None, 1, None, None, None, 0, 1, 1, 1e-3, None, ctypes.byref(d)) == S.EINVAL
+    assert lib.scivr_flow_train_on_batch(None, 1, 1, 1e-3, None, None) == S.EINVAL
+    assert lib.scivr_flow_loss_grad(None, 1, None, None, None, 0, None, None) == S.EINVAL
+    assert lib.scivr_flow_log_density(None, 1, None, None, 0, 0, None, None) == S.EINVAL
+    assert lib.scivr_flow_set_params(None, None, 0, 0, None) == S.EINVAL
+    assert lib.scivr_flow_get_params(None, None, 0) == S.EINVAL
+    assert lib.scivr_flow_sample(None, 0, 0, 1, 0.1, 0.1, None, None, None) == S.EINVAL

@@ -115,3 +115,35 @@ def test_mixed_vs_fp64_gpu_same_samples(scivr):
     assert abs(ng64 - ng32) < 0.02 * n
     c64.close()
     c32.close()
+
+
+def test_mixed_large_f_matches_oracle(scivr, oracle_mod):
+    """One wave per trajectory (F = 24) in the mixed form against the FP64 oracle."""
+    O = oracle_mod
+    F, n, ns, K = 24, 64, 300, 257
+    _say(f"[mixed] F={F} n={n} steps={ns}")
+    prob = inputs.morse_quartic(F, F, n_steps=ns, n_energies=K, e_max=0.2, precision=inputs.PRECISION_MIXED)
+    ctx, I, ng = _run(scivr, prob, 90, n)
+    p0, q0, lr = O.sample_husimi(prob, 90, n)
+    ora = O.run(prob, p0, q0, lr)
+    st = ctx.read_state()
+    flags_o = np.array([ora.state(j).good for j in range(n)])
+    agree = np.mean(flags_o == st["good"].astype(bool))
+    sg = np.sqrt(prob.gamma)
+    errs = []
+    for j in range(n):
+        so = ora.state(j)
+        if not (so.good and st["good"][j]):
+            continue
+        if np.linalg.norm(_parity.scaled_monodromy(prob, so.M)) > 1e2:
+            continue
+        xg = np.concatenate([sg * st["q"][:, j], st["p"][:, j] / sg])
+        xo = np.concatenate([sg * so.q, so.p / sg])
+        errs.append(np.max(np.abs(xg - xo)) / max(1.0, np.max(np.abs(xo))))
+    rel = np.max(np.abs(I - ora.spectrum)) / np.max(ora.spectrum)
+    _say(f"[mixed] F={F} flags {agree:.3f}, {len(errs)} regular, worst state {max(errs) if errs else -1:.2e}, "
+         f"spectrum rel {rel:.2e}")
+    assert agree > 0.9
+    assert len(errs) >= 5 and max(errs) < 1e-4
+    assert rel < 5e-2
+    ctx.close()

@@ -52,6 +52,10 @@ CASES = [
     (3, 257, 400, 130, 0.06, 3),
     (6, 300, 400, 257, 0.1, 6),
     (9, 200, 300, 129, 0.1, 9),
+    # one wave per trajectory (F > 16)
+    (17, 70, 200, 131, 0.15, 17),
+    (30, 48, 120, 257, 0.2, 30),
+    (32, 33, 100, 130, 0.2, 32),
 ]
 
 
@@ -90,15 +94,16 @@ def test_parity_with_oracle(scivr, oracle_mod, F, n, ns, K, emax, sp):
     ctx.close()
 
 
-def test_chunked_propagation_is_identical(scivr):
-    _say("[chunked] F=3")
-    prob = inputs.morse_quartic(3, 3, n_steps=300, n_energies=128)
-    a = _gpu_run(scivr, prob, 5, 200)
-    b = _gpu_run(scivr, prob, 5, 200, chunks=[1, 77, 150])
+@pytest.mark.parametrize("F,n", [(3, 200), (30, 40)])
+def test_chunked_propagation_is_identical(scivr, F, n):
+    _say(f"[chunked] F={F}")
+    prob = inputs.morse_quartic(F, F, n_steps=300, n_energies=128)
+    a = _gpu_run(scivr, prob, 5, n)
+    b = _gpu_run(scivr, prob, 5, n, chunks=[1, 77, 150])
     for k in ("p", "q", "S", "phi", "M", "good", "detM", "maxdev"):
         assert np.array_equal(a[4][k], b[4][k]), k
     assert np.array_equal(a[1], b[1])
-    assert np.array_equal(a[0].read_amplitudes(0, 200), b[0].read_amplitudes(0, 200))
+    assert np.array_equal(a[0].read_amplitudes(0, n), b[0].read_amplitudes(0, n))
 
 
 def test_batches_accumulate_into_one_estimate(scivr, oracle_mod):
