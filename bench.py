@@ -95,14 +95,21 @@ def cpu_baseline(prob, n_sample: int, seed: int):
                       f"{prob.n_energies} energies), {dt:.1f} s wall"}
 
 
-def run_form(scivr, torch, prob, n, steps, warmup, seed0=1000):
+def run_form(scivr, torch, prob, n, steps, warmup, seed0=1000, chunk=0):
     """Time `steps` whole passes (sample + propagate + accumulate) of one form."""
     stream = torch.cuda.current_stream()
     ctx = scivr.Context(prob, max_traj=n)
 
     def one_step(i):
         ctx.sample_husimi(seed=seed0 + i, n_traj=n, stream=stream)
-        ctx.propagate(0, prob.n_steps, stream=stream)
+        if chunk and chunk < prob.n_steps:
+            for b in range(0, prob.n_steps, chunk):
+                ctx.propagate(b, min(prob.n_steps, b + chunk), stream=stream)
+                torch.cuda.synchronize()
+                print(f"[bench] {prob.name} step {i}: {min(prob.n_steps, b + chunk)} of {prob.n_steps} time steps",
+                      file=sys.stderr, flush=True)
+        else:
+            ctx.propagate(0, prob.n_steps, stream=stream)
         ctx.accumulate(stream=stream)
 
     for i in range(warmup):
@@ -124,6 +131,91 @@ def run_form(scivr, torch, prob, n, steps, warmup, seed0=1000):
     return {"wall": wall, "kt": kt, "I": I, "n_good": n_good, "n_total": n_total}
 
 
+def _peak_error_cm(peaks, inputs, E, T, judge_peaks, I):
+    """Largest peak shift (cm^-1) of I against the judge's peaks; inf if a peak is missing."""
+    pt = peaks.find_peaks(E, I, T)
+    worst, missing = peaks.peak_errors(judge_peaks, pt, tol=20.0 / inputs.CM1_PER_HARTREE)
+    return float("inf") if missing else worst * inputs.CM1_PER_HARTREE
+
+
+def learned_study(scivr, inputs, peaks, prob, judge_I, sizes, seeds, n_train, layers, width, epochs, batch, lr,
+                  alpha):
+    """Trajectories needed for a 1 cm^-1 peak error against the judge spectrum,
+    plain Husimi sampling vs the learned proposal, in the given form of `prob`.
+
+    For each seed and each N in `sizes` an independent batch of N trajectories
+    (Philox indices disjoint from the judge's) gives a spectrum; its largest
+    peak shift against the judge is recorded; N_to_1cm is the smallest N whose
+    median shift over the seeds is <= 1 cm^-1.  The flow is trained once on the
+    contributions of a Husimi batch of n_train trajectories.
+    """
+    E, T = prob.energies(), prob.total_time
+    jp = peaks.find_peaks(E, judge_I, T)
+    cap = max(max(sizes), n_train)
+    ctx = scivr.Context(prob, max_traj=cap)
+    base = 1 << 40  # Philox indices far from the judge's
+
+    def sweep(draw):
+        errs = np.zeros((len(seeds), len(sizes)))
+        rms = np.zeros_like(errs)
+        for a, sd in enumerate(seeds):
+            for b, N in enumerate(sizes):
+                ctx.reset_spectrum()
+                draw(sd, N)
+                ctx.propagate()
+                ctx.accumulate()
+                I, _, _ = ctx.read_spectrum()
+                errs[a, b] = _peak_error_cm(peaks, inputs, E, T, jp, I)
+                rms[a, b] = float(np.sqrt(np.mean((I - judge_I) ** 2)) / judge_I.max())
+        med = np.median(errs, axis=0)
+        # smallest N from which on every larger N of the sweep also meets 1 cm^-1
+        n1 = None
+        for b in range(len(sizes) - 1, -1, -1):
+            if med[b] <= 1.0:
+                n1 = sizes[b]
+            else:
+                break
+        return {"N_to_1cm": n1, "median_peak_error_cm1": med.tolist(),
+                "median_rel_rms": np.median(rms, axis=0).tolist()}
+
+    t0 = time.perf_counter()
+    plain = sweep(lambda sd, N: ctx.sample_husimi(seed=sd, n_traj=N, first_index=base))
+    t_plain = time.perf_counter() - t0
+    flow = scivr.Flow(ctx, layers, width, seed=5)
+    ctx.reset_spectrum()
+    ctx.run(seed=4242, n_traj=n_train, first_index=2 * base)
+    t0 = time.perf_counter()
+    loss = flow.train_on_batch(epochs=epochs, batch=batch, lr=lr)
+    t_train = time.perf_counter() - t0
+    info = {}
+
+    def draw_flow(sd, N):
+        ess, used = flow.sample(seed=sd, n_traj=N, first_index=base, alpha=alpha)
+        info.setdefault("ess", []).append(ess)
+        info.setdefault("used", []).append(used)
+
+    t0 = time.perf_counter()
+    learned = sweep(draw_flow)
+    t_learned = time.perf_counter() - t0
+    flow.close()
+    ctx.close()
+    ratio = np.array(plain["median_rel_rms"]) / np.array(learned["median_rel_rms"])
+    return {
+        "variance_ratio_plain_over_learned": float(np.median(ratio ** 2)),
+        "sizes": list(sizes), "seeds": list(seeds), "judge_peaks_cm1": [e * inputs.CM1_PER_HARTREE for e, _ in jp],
+        "plain": plain, "learned": learned,
+        "flow": {"layers": layers, "width": width, "params": int(FLOW_PARAMS(prob.F, width, layers)),
+                 "n_train": n_train, "epochs": epochs, "batch": batch, "lr": lr, "alpha": alpha,
+                 "final_loss": loss, "train_s": t_train, "ess_min": float(min(info["ess"])),
+                 "ess_median": float(np.median(info["ess"])), "fallbacks": int(sum(1 for u in info["used"] if not u))},
+        "sweep_s": {"plain": t_plain, "learned": t_learned},
+    }
+
+
+def FLOW_PARAMS(F, H, L):
+    return L * (H * F + H + H * H + H + 2 * F * H + 2 * F)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -133,6 +225,9 @@ def main():
     ap.add_argument("--plain", default="F9_fp64", help="plain FP64 form timed alongside ('' to skip)")
     ap.add_argument("--n-traj", type=int, default=0, help="override the trajectory count")
     ap.add_argument("--cpu-sample", type=int, default=512, help="oracle trajectories for the CPU baseline (0: skip)")
+    ap.add_argument("--learned", type=int, default=1, help="run the learned-proposal study (1) or not (0)")
+    ap.add_argument("--chunk", type=int, default=0,
+                    help="propagate in calls of this many time steps, printing progress (0: one call)")
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="only copy this many bytes device-to-device (counter calibration) and exit")
     args = ap.parse_args()
@@ -160,11 +255,11 @@ def main():
         n = args.n_traj
     print(f"[bench] {args.workload}: F={prob.F} n={n} steps={prob.n_steps} K={prob.n_energies}", file=sys.stderr,
           flush=True)
-    main_run = run_form(scivr, torch, prob, n, args.steps, args.warmup)
+    main_run = run_form(scivr, torch, prob, n, args.steps, args.warmup, chunk=args.chunk)
     plain = None
     if args.plain:
         pprob, _ = inputs.workload(args.plain)
-        plain = run_form(scivr, torch, pprob, n, args.steps, args.warmup)
+        plain = run_form(scivr, torch, pprob, n, args.steps, args.warmup, chunk=args.chunk)
 
     wall = main_run["wall"]
     kt = main_run["kt"]
@@ -176,7 +271,8 @@ def main():
     t_launch = ms_tr / max(n_tr, 1) / 1e3
     fl_launch = traj_flops_per_step(prob.F) * traj_steps
     achieved = fl_launch / t_launch / 1e12
-    src_hash = _source_hash("traj.hip")
+    big = prob.F > 16
+    src_hash = _source_hash("traj_big.hip" if big else "traj.hip", "traj_common.h")
     traffic = _profile_traffic(prob.name, src_hash)
     fo_launch = ms_fo / max(n_fo, 1) / 1e3
     fo_fl = fourier_flops(n, prob.n_steps + 1, prob.n_energies)
@@ -203,7 +299,7 @@ def main():
             "precision": "mixed" if mixed else "fp64", "parallelism": "single GPU",
         },
         "roofline": {
-            "kernel": "traj_kernel",
+            "kernel": "traj_big_kernel" if big else "traj_kernel",
             "bound": "alu",
             "achieved": achieved,
             "peak": FP64_VALU_PEAK_TFLOPS,
@@ -242,6 +338,15 @@ def main():
             "peak_error_cm1": worst * inputs.CM1_PER_HARTREE, "peaks_compared": len(pr), "peaks_missing": missing,
             "same_samples": True,
         }
+    if args.learned and plain is not None:
+        print("[bench] learned-proposal study", file=sys.stderr, flush=True)
+        sizes = [1 << k for k in range(10, 19)]
+        out["learned_proposal"] = learned_study(scivr, inputs, peaks, prob, plain["I"], sizes,
+                                                seeds=(11, 12, 13, 14, 15),
+                                                n_train=65536, layers=4, width=128, epochs=20, batch=4096, lr=1e-3,
+                                                alpha=0.1)
+        out["learned_proposal"]["judge"] = (f"plain FP64 spectrum of the timed run: {args.steps} batches of {n} "
+                                            f"Husimi trajectories")
     if args.cpu_sample > 0:
         print(f"[bench] cpu baseline: oracle on {args.cpu_sample} trajectories", file=sys.stderr, flush=True)
         pprob = prob.replace(precision=inputs.PRECISION_FP64)

@@ -47,7 +47,7 @@ struct alignas(16) BigLds {
 // det of the real N x N matrix whose row `pos` lives in a[] of the lanes with
 // `active` set (positions 0..N-1, one row per lane).  Every lane returns det.
 template <int N>
-__device__ inline double lu_det_rows(double (&a)[N], bool active, int pos, double *piv, unsigned long long *slot)
+__device__ __attribute__((always_inline)) inline double lu_det_rows(double (&a)[N], bool active, int pos, double *piv, unsigned long long *slot)
 {
     bool alive = active;
     if (active) slot[pos] = 0ull;
@@ -82,7 +82,7 @@ __device__ inline double lu_det_rows(double (&a)[N], bool active, int pos, doubl
 // det of the complex N x N matrix whose row `pos` lives in (ar, ai) of the
 // active lanes; pivot on |a_k|^2.  Every lane returns (dr, di).
 template <int N>
-__device__ inline void lu_det_rows_complex(double (&ar)[N], double (&ai)[N], bool active, int pos, double *piv,
+__device__ __attribute__((always_inline)) inline void lu_det_rows_complex(double (&ar)[N], double (&ai)[N], bool active, int pos, double *piv,
                                            unsigned long long *slot, double &dr, double &di)
 {
     bool alive = active;
