@@ -16,9 +16,11 @@
 //    row i of the Herman-Kluk prefactor matrix A of Eq. (5) from rows i and
 //    F + i, and lane r < 2F takes row r of M; det(A) (complex) and det(M)
 //    (real, the stability monitor after Eq. (5)) follow by Gaussian
-//    elimination with partial pivoting across the lanes, one row per lane,
-//    exactly as in the small-F kernel (LDS atomic max over packed (|a|,
-//    position) keys picks each pivot, the pivot lane publishes its row);
+//    elimination with partial pivoting across the lanes, one row per lane:
+//    a wave-wide DPP maximum over packed (|a|, position) keys picks each
+//    pivot (the trajectory is the whole wave, so the pivot is wave-uniform)
+//    and the pivot row reaches every lane through readlane into scalar
+//    registers, with no LDS round trip in the elimination;
 //  * lane 0 keeps the action, the continuous prefactor phase and writes the
 //    amplitude of the time sample.
 // The state layout, the branch tracking and the amplitude storage (FP64
@@ -40,91 +42,111 @@ struct alignas(16) BigLds {
     static constexpr int RS = N2 + 1;  // odd row stride of the transpose buffer
     double T[N2 * RS];                 // M, row r at T + r RS
     double lam[F * F];                 // coupling matrix, row-major, zero diagonal
-    double piv[N2];                    // pivot row (complex elimination: re, im interleaved)
-    unsigned long long slot[N2];       // per-column argmax keys
 };
 
+// Largest 64-bit key over the wave (every lane gets it).  DPP row shifts
+// 1, 2, 4, 8 leave each row's maximum in its lane 15, row broadcasts 15 and 31
+// carry it to lane 63; lanes without a source take the identity 0.
+__device__ __attribute__((always_inline)) inline unsigned long long wave_max_u64(unsigned long long v)
+{
+    unsigned lo = (unsigned)v, hi = (unsigned)(v >> 32);
+#define SCIVR_DPP_MAX(ctrl, rmask)                                                                    \
+    {                                                                                                 \
+        const unsigned olo = (unsigned)__builtin_amdgcn_update_dpp(0, (int)lo, ctrl, rmask, 0xf, false); \
+        const unsigned ohi = (unsigned)__builtin_amdgcn_update_dpp(0, (int)hi, ctrl, rmask, 0xf, false); \
+        const bool gt = ohi > hi || (ohi == hi && olo > lo);                                          \
+        lo = gt ? olo : lo;                                                                           \
+        hi = gt ? ohi : hi;                                                                           \
+    }
+    SCIVR_DPP_MAX(0x111, 0xf)  // row_shr:1
+    SCIVR_DPP_MAX(0x112, 0xf)  // row_shr:2
+    SCIVR_DPP_MAX(0x114, 0xf)  // row_shr:4
+    SCIVR_DPP_MAX(0x118, 0xf)  // row_shr:8
+    SCIVR_DPP_MAX(0x142, 0xa)  // row_bcast:15 into rows 1 and 3
+    SCIVR_DPP_MAX(0x143, 0xc)  // row_bcast:31 into rows 2 and 3
+#undef SCIVR_DPP_MAX
+    lo = (unsigned)__builtin_amdgcn_readlane((int)lo, 63);
+    hi = (unsigned)__builtin_amdgcn_readlane((int)hi, 63);
+    return ((unsigned long long)hi << 32) | lo;
+}
+
+// The value of v in lane l (l uniform across the wave), into scalar registers.
+__device__ __attribute__((always_inline)) inline double readlane_f64(double v, int l)
+{
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+    return __hiloint2double(hi, lo);
+}
+
+// Lane of the live row at position ppos (exactly one).
+__device__ __attribute__((always_inline)) inline int pivot_lane(bool alive, int pos, int ppos)
+{
+    const unsigned long long m = __ballot(alive && pos == ppos);
+    return __builtin_ctzll(m);
+}
+
 // det of the real N x N matrix whose row `pos` lives in a[] of the lanes with
-// `active` set (positions 0..N-1, one row per lane).  Every lane returns det.
+// `active` set (positions 0..N-1, one row per lane of the wave).  The pivot of
+// each column is the live row with the largest |a_k| (ties to the lowest
+// position, as in a row-swapping LU), found by a wave-wide maximum; its row is
+// read into scalar registers lane by lane, so the elimination needs no LDS.
+// The row at position k and the pivot swap positions; the determinant
+// changes sign when they differ.  Every lane returns det.
 template <int N>
-__device__ __attribute__((always_inline)) inline double lu_det_rows(double (&a)[N], bool active, int pos, double *piv, unsigned long long *slot)
+__device__ __attribute__((always_inline)) inline double lu_det_rows(double (&a)[N], bool active, int pos)
 {
     bool alive = active;
-    if (active) slot[pos] = 0ull;
     double det = 1.0;
 #pragma unroll
     for (int k = 0; k < N; ++k) {
-        lds_order();
-        if (alive) atomicMax(&slot[k], pivot_key(fabs(a[k]), pos));
-        lds_order();
-        const unsigned long long win = __hip_atomic_load(&slot[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+        const unsigned long long win = wave_max_u64(alive ? pivot_key(fabs(a[k]), pos) : 0ull);
         const int ppos = 63 - (int)(win & 63ull);
+        const int pl = pivot_lane(alive, pos, ppos);
         const bool isp = alive && pos == ppos;
-        if (isp) {
-#pragma unroll
-            for (int jj = k; jj < N; ++jj) piv[jj] = a[jj];
-        }
-        lds_order();
-        const double pk = piv[k];
+        const double pk = readlane_f64(a[k], pl);
         det *= (ppos != k) ? -pk : pk;
         pos = (alive && pos == k) ? ppos : pos;
         alive = alive && !isp;
-        if (alive) {
-            const double l = a[k] * rcp_nr(pk);
+        const double l = alive ? a[k] * rcp_nr(pk) : 0.0;
 #pragma unroll
-            for (int jj = k + 1; jj < N; ++jj) a[jj] = fma(-l, piv[jj], a[jj]);
-        }
+        for (int jj = k + 1; jj < N; ++jj) a[jj] = fma(-l, readlane_f64(a[jj], pl), a[jj]);
     }
-    lds_order();
     return det;
 }
 
 // det of the complex N x N matrix whose row `pos` lives in (ar, ai) of the
-// active lanes; pivot on |a_k|^2.  Every lane returns (dr, di).
+// active lanes; pivot on |a_k|^2, otherwise as lu_det_rows.
 template <int N>
-__device__ __attribute__((always_inline)) inline void lu_det_rows_complex(double (&ar)[N], double (&ai)[N], bool active, int pos, double *piv,
-                                           unsigned long long *slot, double &dr, double &di)
+__device__ __attribute__((always_inline)) inline void lu_det_rows_complex(double (&ar)[N], double (&ai)[N],
+                                                                          bool active, int pos, double &dr,
+                                                                          double &di)
 {
     bool alive = active;
-    if (active) slot[pos] = 0ull;
     double zr = 1.0, zi = 0.0;
 #pragma unroll
     for (int k = 0; k < N; ++k) {
         const double m2 = fma(ar[k], ar[k], ai[k] * ai[k]);
-        lds_order();
-        if (alive) atomicMax(&slot[k], pivot_key(m2, pos));
-        lds_order();
-        const unsigned long long win = __hip_atomic_load(&slot[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+        const unsigned long long win = wave_max_u64(alive ? pivot_key(m2, pos) : 0ull);
         const int ppos = 63 - (int)(win & 63ull);
+        const int pl = pivot_lane(alive, pos, ppos);
         const bool isp = alive && pos == ppos;
-        if (isp) {
-#pragma unroll
-            for (int jj = k; jj < N; ++jj) {
-                piv[2 * jj] = ar[jj];
-                piv[2 * jj + 1] = ai[jj];
-            }
-        }
-        lds_order();
-        const double pr = piv[2 * k], pi = piv[2 * k + 1];
+        const double pr = readlane_f64(ar[k], pl), pi = readlane_f64(ai[k], pl);
         const double nr = zr * pr - zi * pi;
         const double ni = zr * pi + zi * pr;
         zr = (ppos != k) ? -nr : nr;
         zi = (ppos != k) ? -ni : ni;
         pos = (alive && pos == k) ? ppos : pos;
         alive = alive && !isp;
-        if (alive) {
-            const double inv = rcp_nr(fma(pr, pr, pi * pi));
-            const double lr = (ar[k] * pr + ai[k] * pi) * inv;
-            const double li = (ai[k] * pr - ar[k] * pi) * inv;
+        const double inv = rcp_nr(fma(pr, pr, pi * pi));
+        const double lr = alive ? (ar[k] * pr + ai[k] * pi) * inv : 0.0;
+        const double li = alive ? (ai[k] * pr - ar[k] * pi) * inv : 0.0;
 #pragma unroll
-            for (int jj = k + 1; jj < N; ++jj) {
-                const double br = piv[2 * jj], bi = piv[2 * jj + 1];
-                ar[jj] = ar[jj] - (lr * br - li * bi);
-                ai[jj] = ai[jj] - (lr * bi + li * br);
-            }
+        for (int jj = k + 1; jj < N; ++jj) {
+            const double br = readlane_f64(ar[jj], pl), bi = readlane_f64(ai[jj], pl);
+            ar[jj] = ar[jj] - (lr * br - li * bi);
+            ai[jj] = ai[jj] - (lr * bi + li * br);
         }
     }
-    lds_order();
     dr = zr;
     di = zi;
 }
@@ -347,7 +369,7 @@ traj_big_kernel(TrajArgs A, const ProblemDev *__restrict__ P0)
                 are[jj] = 0.5 * (sgc * r1[F + jj] * isj + r0[jj] * sj * isgc);
                 aim[jj] = 0.5 * (-sgc * r1[jj] * sj + r0[F + jj] * isgc * isj);
             }
-            lu_det_rows_complex<F>(are, aim, modeLane, lane, L.piv, L.slot, dAr, dAi);
+            lu_det_rows_complex<F>(are, aim, modeLane, lane, dAr, dAi);
         }
 
         // stability monitor |det(M)^2 - 1| on checked steps, row `lane` (< 2F) of M per lane
@@ -357,7 +379,7 @@ traj_big_kernel(TrajArgs A, const ProblemDev *__restrict__ P0)
             const double *row = L.T + (colLane ? lane : 0) * RS;
 #pragma unroll
             for (int jj = 0; jj < N2; ++jj) a[jj] = row[jj];
-            const double dM = lu_det_rows<N2>(a, colLane, lane, L.piv, L.slot);
+            const double dM = lu_det_rows<N2>(a, colLane, lane);
             const double dev = fabs(dM * dM - 1.0);
             detM = dM;
             if (!(dev <= maxdev)) maxdev = dev;
