@@ -7,14 +7,15 @@
 //    initial directions p0_c and q0_c; it also carries the trajectory's p and
 //    q, and evaluates the Morse terms of mode c, which it shares with the
 //    group through LDS;
-//  * after each step M is transposed through LDS so that lane c holds rows c
-//    and F + c; from them it forms row c of the Herman-Kluk prefactor matrix A
-//    of Eq. (5) locally, and the group takes det(A) (complex, F x F, one row
-//    per lane) and det(M) (real, 2F x 2F, two rows per lane; the stability
-//    monitor after Eq. (5)) by Gaussian elimination with partial pivoting
-//    across its lanes: one LDS atomic max over packed (|a|, position) keys
-//    picks each pivot, the pivot lane publishes its row, the live rows read it
-//    back as a broadcast.
+//  * after each step the group takes det(A) of the Herman-Kluk prefactor
+//    matrix of Eq. (5) (complex, F x F) and det(M) (real, 2F x 2F; the
+//    stability monitor after Eq. (5)) as the determinants of the transposes,
+//    whose rows are the columns lane c already holds: column c of A (one row of
+//    A^T per lane) and columns c, F + c of M (two rows of M^T per lane), so
+//    no transpose is needed.  Gaussian elimination with partial pivoting runs
+//    across the group's lanes: one LDS atomic max over packed (|a|, position)
+//    keys picks each pivot, the pivot lane publishes its row, the live rows
+//    read it back as a broadcast.
 //
 // The fourth-order symplectic step is the drift-kick-drift triple jump
 // (Yoshida / Forest-Ruth); each kick evaluates gradient, Hessian and potential
@@ -42,12 +43,16 @@ namespace {
 template <int F>
 struct alignas(16) GroupLds {
     static constexpr int N2 = 2 * F;
-    static constexpr int RS = N2;      // row stride of the half-matrix transpose buffer
-    double T[F * RS];                  // one half (F rows) of the transposed monodromy matrix
+    // bytes of the fields below; the padding makes the stride between groups
+    // 16 B more than a multiple of the 256-byte bank row, so the groups'
+    // simultaneous broadcast reads fall into different banks
+    static constexpr int BYTES = 8 * (3 * N2 + F + (F & 1));
+    static constexpr int PAD = ((16 - BYTES % 256) % 256 + 256) % 256 / 8;
     double pivM[N2];                   // pivot row of the real elimination
     double pivA[N2];                   // pivot row of the complex elimination (re, im interleaved)
     unsigned long long slotM[N2];      // per-step argmax keys of the two eliminations
     unsigned long long slotA[F + (F & 1)];
+    double pad[PAD > 0 ? PAD : 2];
 };
 
 // det of the real N x N matrix (N = 2F) whose rows at positions pos0, pos1
@@ -175,7 +180,6 @@ traj_kernel(TrajArgs A, const ProblemDev *__restrict__ P0)
     typedef typename std::conditional<MIXED, float, double>::type R;
     constexpr int N2 = 2 * F;
     constexpr int TPW = 64 / F;
-    constexpr int RS = GroupLds<F>::RS;
     __shared__ GroupLds<F> lds_all[TPW];
     __shared__ double lam_lds[F * F];  // coupling matrix, shared by the wave's groups
     __shared__ R qv_all[TPW][F + (F & 1)], pm_all[TPW][F + (F & 1)];
@@ -381,36 +385,20 @@ traj_kernel(TrajArgs A, const ProblemDev *__restrict__ P0)
         const int stp = step + 1;
         const double t = (double)stp * Ps->dt;
 
-        // ---- transpose M through LDS in two halves: lane c ends with rows c and F + c ----
-        double r0[N2], r1[N2];  // rows c (p_c) and F + c (q_c)
-#pragma unroll
-        for (int i = 0; i < F; ++i) {
-            L.T[i * RS + c] = dpP[i];
-            L.T[i * RS + F + c] = dpQ[i];
-        }
-        lds_order();
-#pragma unroll
-        for (int jj = 0; jj < N2; ++jj) r0[jj] = L.T[c * RS + jj];
-        lds_order();
-#pragma unroll
-        for (int i = 0; i < F; ++i) {
-            L.T[i * RS + c] = dqP[i];
-            L.T[i * RS + F + c] = dqQ[i];
-        }
-        lds_order();
-#pragma unroll
-        for (int jj = 0; jj < N2; ++jj) r1[jj] = L.T[c * RS + jj];
-        lds_order();
-
-        // prefactor matrix row c from rows c (Mpp, Mpq) and F + c (Mqp, Mqq), then det(A)
+        // det(A) = det(A^T) and det(M) = det(M^T): the rows of the transposes are
+        // columns, and lane c already holds columns c (d/dp0_c) and F + c
+        // (d/dq0_c) of M, so it forms column c of A and rows c, F + c of M^T
+        // from its own registers, with no transpose.
         double dAr, dAi;
         {
             double are[F], aim[F];
 #pragma unroll
-            for (int jj = 0; jj < F; ++jj) {
-                const double sj = Ps->sqrt_gamma[jj], isj = Ps->inv_sqrt_gamma[jj];
-                are[jj] = 0.5 * (sgc * r1[F + jj] * isj + r0[jj] * sj * isgc);
-                aim[jj] = 0.5 * (-sgc * r1[jj] * sj + r0[F + jj] * isgc * isj);
+            for (int i = 0; i < F; ++i) {
+                const double si = Ps->sqrt_gamma[i], isi = Ps->inv_sqrt_gamma[i];
+                // A[i][c] = (1/2)[sqrt(g_i) Mqq[i][c] / sqrt(g_c) + Mpp[i][c] sqrt(g_c) / sqrt(g_i)]
+                //         + (i/2)[-sqrt(g_i) Mqp[i][c] sqrt(g_c) + Mpq[i][c] / (sqrt(g_i) sqrt(g_c))]
+                are[i] = 0.5 * (si * dqQ[i] * isgc + dpP[i] * sgc * isi);
+                aim[i] = 0.5 * (-si * dqP[i] * sgc + dpQ[i] * isi * isgc);
             }
             lu_det_complex<F>(are, aim, c, L.pivA, L.slotA, dAr, dAi);
         }
@@ -418,6 +406,14 @@ traj_kernel(TrajArgs A, const ProblemDev *__restrict__ P0)
         // stability monitor |det(M)^2 - 1| on checked steps
         const bool checked = (A.check_every <= 1) || (stp % A.check_every == 0) || (stp == A.n_steps);
         if (checked) {
+            double r0[N2], r1[N2];  // rows c and F + c of M^T, entries ordered (p rows, q rows) of M
+#pragma unroll
+            for (int i = 0; i < F; ++i) {
+                r0[i] = dpP[i];
+                r0[F + i] = dqP[i];
+                r1[i] = dpQ[i];
+                r1[F + i] = dqQ[i];
+            }
             const double dM = lu_det_real2<N2>(r0, r1, c, F + c, L.pivM, L.slotM);
             const double dev = fabs(dM * dM - 1.0);
             detM = dM;
