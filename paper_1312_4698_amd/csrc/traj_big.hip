@@ -9,14 +9,14 @@
 //    and kicks), each kick applying the Hessian to the lane's tangent column
 //    in factored form H dq = h o dq + 4 q o (Lambda (q o dq)) with the coupling
 //    matrix Lambda as scalar operands;
-//  * M is written to LDS column by column and read back row by row (odd row
-//    stride, so both directions are free of bank conflicts), and each lane
-//    reloads its column afterwards (so the register copy is dead while the
-//    eliminations run): lane i < F forms
-//    row i of the Herman-Kluk prefactor matrix A of Eq. (5) from rows i and
-//    F + i, and lane r < 2F takes row r of M; det(A) (complex) and det(M)
-//    (real, the stability monitor after Eq. (5)) follow by Gaussian
-//    elimination with partial pivoting across the lanes, one row per lane:
+//  * det(A) of the Herman-Kluk prefactor matrix of Eq. (5) and det(M) (the
+//    stability monitor after Eq. (5)) are taken as the determinants of the
+//    transposes: lane c < 2F's own column is row c of M^T, and lane i < F
+//    forms column i of A from its own column and column F + i, which it reads
+//    from an LDS copy of M (written column by column; each lane also reloads
+//    its column from it afterwards, so the register copy is dead while the
+//    eliminations run).  Gaussian elimination with partial pivoting runs
+//    across the lanes, one row per lane:
 //    a wave-wide DPP maximum over packed (|a|, position) keys picks each
 //    pivot (the trajectory is the whole wave, so the pivot is wave-uniform)
 //    and the pivot row reaches every lane through readlane into scalar
@@ -357,28 +357,34 @@ traj_big_kernel(TrajArgs A, const ProblemDev *__restrict__ P0)
         }
         lds_order();
 
-        // prefactor matrix row `lane` (< F) from rows lane (Mpp, Mpq) and F + lane (Mqp, Mqq); det(A)
+        // det(A) = det(A^T) and det(M) = det(M^T): lane c < F forms column c of A
+        // from its own column (Mpp[.][c], Mqp[.][c]) and column F + c (Mpq, Mqq)
+        // read from LDS; lane c < 2F holds row c of M^T, its own column
         double dAr, dAi;
         {
             const double sgc = Ps->sqrt_gamma[cm], isgc = Ps->inv_sqrt_gamma[cm];
-            const double *r0 = L.T + cm * RS, *r1 = L.T + (F + cm) * RS;
             double are[F], aim[F];
 #pragma unroll
-            for (int jj = 0; jj < F; ++jj) {
-                const double sj = Ps->sqrt_gamma[jj], isj = Ps->inv_sqrt_gamma[jj];
-                are[jj] = 0.5 * (sgc * r1[F + jj] * isj + r0[jj] * sj * isgc);
-                aim[jj] = 0.5 * (-sgc * r1[jj] * sj + r0[F + jj] * isgc * isj);
+            for (int i = 0; i < F; ++i) {
+                const double si = Ps->sqrt_gamma[i], isi = Ps->inv_sqrt_gamma[i];
+                const double mpq = L.T[i * RS + F + cm], mqq = L.T[(F + i) * RS + F + cm];
+                // A[i][c] = (1/2)[sqrt(g_i) Mqq[i][c] / sqrt(g_c) + Mpp[i][c] sqrt(g_c) / sqrt(g_i)]
+                //         + (i/2)[-sqrt(g_i) Mqp[i][c] sqrt(g_c) + Mpq[i][c] / (sqrt(g_i) sqrt(g_c))]
+                are[i] = 0.5 * (si * mqq * isgc + dp[i] * sgc * isi);
+                aim[i] = 0.5 * (-si * dq[i] * sgc + mpq * isi * isgc);
             }
             lu_det_rows_complex<F>(are, aim, modeLane, lane, dAr, dAi);
         }
 
-        // stability monitor |det(M)^2 - 1| on checked steps, row `lane` (< 2F) of M per lane
+        // stability monitor |det(M)^2 - 1| on checked steps
         const bool checked = (A.check_every <= 1) || (stp % A.check_every == 0) || (stp == A.n_steps);
         if (checked) {
             double a[N2];
-            const double *row = L.T + (colLane ? lane : 0) * RS;
 #pragma unroll
-            for (int jj = 0; jj < N2; ++jj) a[jj] = row[jj];
+            for (int i = 0; i < F; ++i) {
+                a[i] = dp[i];
+                a[F + i] = dq[i];
+            }
             const double dM = lu_det_rows<N2>(a, colLane, lane);
             const double dev = fabs(dM * dM - 1.0);
             detM = dM;
