@@ -347,6 +347,20 @@ def main():
                                                 alpha=0.1)
         out["learned_proposal"]["judge"] = (f"plain FP64 spectrum of the timed run: {args.steps} batches of {n} "
                                             f"Husimi trajectories")
+        lp = out["learned_proposal"]
+        vp, vm = out["plain_fp64"]["value"], value
+        n_plain, n_learn = lp["plain"]["N_to_1cm"], lp["learned"]["N_to_1cm"]
+        train_s = lp["flow"]["train_s"] + lp["flow"]["n_train"] * prob.n_steps / vm
+        out["time_to_1cm"] = {
+            "plain_fp64_s": None if n_plain is None else n_plain * prob.n_steps / vp,
+            "plain_fp64_lower_bound_s": sizes[-1] * prob.n_steps / vp if n_plain is None else None,
+            "mixed_learned_s": None if n_learn is None else n_learn * prob.n_steps / vm + train_s,
+            "mixed_learned_training_s": train_s,
+            "equal_variance_speedup": lp["variance_ratio_plain_over_learned"] * vm / vp,
+            "note": ("plain: FP64 path with Husimi sampling; mixed_learned: mixed path with the learned proposal, "
+                     "including its training batch and training time; equal_variance_speedup = (plain/learned "
+                     "spectrum variance at equal N) x (mixed/plain throughput)"),
+        }
     if args.cpu_sample > 0:
         print(f"[bench] cpu baseline: oracle on {args.cpu_sample} trajectories", file=sys.stderr, flush=True)
         pprob = prob.replace(precision=inputs.PRECISION_FP64)

@@ -6,9 +6,11 @@
 // q half dq[]); lane i < F also owns mode i of the trajectory (p_i, q_i and the
 // Morse terms of that mode), shared with the wave through LDS.  Per step:
 //  * the fourth-order symplectic triple jump (Yoshida / Forest-Ruth drifts
-//    and kicks), each kick applying the Hessian to the lane's tangent column
-//    in factored form H dq = h o dq + 4 q o (Lambda (q o dq)) with the coupling
-//    matrix Lambda as scalar operands;
+//    and kicks), each kick applying the Hessian to all tangent columns in
+//    factored form H dq = h o dq + 4 q o (Lambda (q o dq)); the product of the
+//    coupling matrix Lambda with the 2F columns q o dq is one 32 x 32 by
+//    32 x 64 FP64 matrix-core product per kick (the batched monodromy product),
+//    staged through LDS between the column-per-lane and the MFMA layouts;
 //  * det(A) of the Herman-Kluk prefactor matrix of Eq. (5) and det(M) (the
 //    stability monitor after Eq. (5)) are taken as the determinants of the
 //    transposes: lane c < 2F's own column is row c of M^T, and lane i < F
@@ -39,10 +41,16 @@ namespace {
 template <int F>
 struct alignas(16) BigLds {
     static constexpr int N2 = 2 * F;
-    static constexpr int RS = N2 + 1;  // odd row stride of the transpose buffer
-    double T[N2 * RS];                 // M, row r at T + r RS
-    double lam[F * F];                 // coupling matrix, row-major, zero diagonal
+    static constexpr int RS = N2 + 1;  // odd row stride of the copy of M
+    static constexpr int US = 65;      // row stride of the kick's 32 x 64 operand / result staging
+    union {
+        double T[N2 * RS];  // M, row r at T + r RS (after the step)
+        double U[32 * US];  // q o dq, then Lambda (q o dq), row i at U + i US (during the kicks)
+    };
+    double lam[F * F];  // coupling matrix, row-major, zero diagonal
 };
+
+typedef double d4 __attribute__((ext_vector_type(4)));
 
 // Largest 64-bit key over the wave (every lane gets it).  DPP row shifts
 // 1, 2, 4, 8 leave each row's maximum in its lane 15, row broadcasts 15 and 31
@@ -172,6 +180,18 @@ traj_big_kernel(TrajArgs A, const ProblemDev *__restrict__ P0)
     const int cm = modeLane ? lane : 0;
 
     const R kc = (R)P->k[cm], Dc = (R)P->D[cm], ac = (R)P->a[cm];
+    constexpr int US = BigLds<F>::US;
+    const int li = lane & 15, kg = lane >> 4;
+    // A-operand fragments of Lambda (32 x 32, zero-padded): block (ib, kb) holds
+    // Lambda[16 ib + li][4 kb + kg] in this lane
+    double lamA[2][8];
+#pragma unroll
+    for (int ib = 0; ib < 2; ++ib)
+#pragma unroll
+        for (int kb = 0; kb < 8; ++kb) {
+            const int r = 16 * ib + li, cc = 4 * kb + kg;
+            lamA[ib][kb] = (r < F && cc < F) ? P->lam[r * FMAX + cc] : 0.0;
+        }
 
     double dp[F], dq[F];  // column `lane` of M: p rows and q rows
     R pc = 0, qc = 0;     // mode `lane` of the trajectory (lanes < F)
@@ -320,25 +340,43 @@ traj_big_kernel(TrajArgs A, const ProblemDev *__restrict__ P0)
                 for (int i = 0; i < F; ++i) V += pv[i];
                 S.add(-hk * (double)V);
             }
-            // tangent kick of column `lane`: dp -= hk (h o dq + 4 q o Lambda (q o dq))
-            if (colLane) {
-                double u[F];
+            // tangent kick of every column: dp -= hk (h o dq + 4 q o W), W = Lambda (q o dq),
+            // the 32 x 32 by 32 x 64 product on the matrix cores (v_mfma_f64_16x16x4f64:
+            // A[i][k] in lane i + 16 k, B[k][j] in lane j + 16 k, D[i][j] in lane
+            // j + 16 (i mod 4), register i / 4); operands and result pass through LDS
 #pragma unroll
-                for (int i = 0; i < F; ++i) u[i] = (double)qv[i] * dq[i];
+            for (int i = 0; i < 32; ++i)
+                L.U[i * US + lane] = (i < F && colLane) ? (double)qv[i < F ? i : 0] * dq[i < F ? i : 0] : 0.0;
+            lds_order();
+            d4 acc[2][4];
+#pragma unroll
+            for (int ib = 0; ib < 2; ++ib)
+#pragma unroll
+                for (int cb = 0; cb < 4; ++cb) acc[ib][cb] = (d4){0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int kb = 0; kb < 8; ++kb) {
+                double b[4];
+#pragma unroll
+                for (int cb = 0; cb < 4; ++cb) b[cb] = L.U[(4 * kb + kg) * US + 16 * cb + li];
+#pragma unroll
+                for (int ib = 0; ib < 2; ++ib)
+#pragma unroll
+                    for (int cb = 0; cb < 4; ++cb)
+                        acc[ib][cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(lamA[ib][kb], b[cb], acc[ib][cb], 0, 0, 0);
+            }
+            lds_order();
+#pragma unroll
+            for (int ib = 0; ib < 2; ++ib)
+#pragma unroll
+                for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) L.U[(16 * ib + 4 * r + kg) * US + 16 * cb + li] = acc[ib][cb][r];
+            lds_order();
+            if (colLane) {
 #pragma unroll
                 for (int i = 0; i < F; ++i) {
-                    double w0 = 0.0, w1 = 0.0;
-#pragma unroll
-                    for (int jj = 0; jj < F; ++jj) {
-                        if (jj == i) continue;
-                        const double l = Pk->lam[i * FMAX + jj];
-                        if (jj & 1)
-                            w1 = fma(l, u[jj], w1);
-                        else
-                            w0 = fma(l, u[jj], w0);
-                    }
                     const double qi = (double)qv[i];
-                    dp[i] = fma(-hk, fma((double)phd[i], dq[i], 4.0 * qi * (w0 + w1)), dp[i]);
+                    dp[i] = fma(-hk, fma((double)phd[i], dq[i], 4.0 * qi * L.U[i * US + lane]), dp[i]);
                 }
             }
             lds_order();
