@@ -268,8 +268,11 @@ def main():
     value = traj_steps / (wall / args.steps)
     n_tr, ms_tr = kt["trajectory"]
     n_fo, ms_fo = kt["fourier"]
+    # one pass may be several trajectory launches (chunked propagation): the
+    # rate is the pass's algorithmic flops over the summed launch durations
     t_launch = ms_tr / max(n_tr, 1) / 1e3
-    fl_launch = traj_flops_per_step(prob.F) * traj_steps
+    launches_per_pass = max(n_tr, 1) / args.steps
+    fl_launch = traj_flops_per_step(prob.F) * traj_steps / launches_per_pass
     achieved = fl_launch / t_launch / 1e12
     big = prob.F > 16
     src_hash = _source_hash("traj_big.hip" if big else "traj.hip", "traj_common.h")
@@ -335,6 +338,7 @@ def main():
             "trajectory_ms": plain["kt"]["trajectory"][1] / max(plain["kt"]["trajectory"][0], 1),
             "fourier_ms": plain["kt"]["fourier"][1] / max(plain["kt"]["fourier"][0], 1),
             "speedup_of_value": value / pv,
+            "n_good_fraction": plain["n_good"] / max(plain["n_total"], 1),
             "peak_error_cm1": worst * inputs.CM1_PER_HARTREE, "peaks_compared": len(pr), "peaks_missing": missing,
             "same_samples": True,
         }
