@@ -131,29 +131,29 @@ def run_form(scivr, torch, prob, n, steps, warmup, seed0=1000, chunk=0):
     return {"wall": wall, "kt": kt, "I": I, "n_good": n_good, "n_total": n_total}
 
 
-def _peak_error_cm(peaks, inputs, E, T, judge_peaks, I):
-    """Largest peak shift (cm^-1) of I against the judge's peaks; inf if a peak is missing."""
+def _peak_error_cm(peaks, inputs, E, T, ref_peaks, I):
+    """Largest peak shift (cm^-1) of I against the reference peaks; inf if a peak is missing."""
     pt = peaks.find_peaks(E, I, T)
-    worst, missing = peaks.peak_errors(judge_peaks, pt, tol=20.0 / inputs.CM1_PER_HARTREE)
+    worst, missing = peaks.peak_errors(ref_peaks, pt, tol=20.0 / inputs.CM1_PER_HARTREE)
     return float("inf") if missing else worst * inputs.CM1_PER_HARTREE
 
 
-def learned_study(scivr, inputs, peaks, prob, judge_I, sizes, seeds, n_train, layers, width, epochs, batch, lr,
+def learned_study(scivr, inputs, peaks, prob, ref_I, sizes, seeds, n_train, layers, width, epochs, batch, lr,
                   alpha):
-    """Trajectories needed for a 1 cm^-1 peak error against the judge spectrum,
+    """Trajectories needed for a 1 cm^-1 peak error against the reference spectrum,
     plain Husimi sampling vs the learned proposal, in the given form of `prob`.
 
     For each seed and each N in `sizes` an independent batch of N trajectories
-    (Philox indices disjoint from the judge's) gives a spectrum; its largest
-    peak shift against the judge is recorded; N_to_1cm is the smallest N whose
+    (Philox indices disjoint from the reference run's) gives a spectrum; its largest
+    peak shift against the reference is recorded; N_to_1cm is the smallest N whose
     median shift over the seeds is <= 1 cm^-1.  The flow is trained once on the
     contributions of a Husimi batch of n_train trajectories.
     """
     E, T = prob.energies(), prob.total_time
-    jp = peaks.find_peaks(E, judge_I, T)
+    jp = peaks.find_peaks(E, ref_I, T)
     cap = max(max(sizes), n_train)
     ctx = scivr.Context(prob, max_traj=cap)
-    base = 1 << 40  # Philox indices far from the judge's
+    base = 1 << 40  # Philox indices far from the reference run's
 
     def sweep(draw):
         errs = np.zeros((len(seeds), len(sizes)))
@@ -166,7 +166,7 @@ def learned_study(scivr, inputs, peaks, prob, judge_I, sizes, seeds, n_train, la
                 ctx.accumulate()
                 I, _, _ = ctx.read_spectrum()
                 errs[a, b] = _peak_error_cm(peaks, inputs, E, T, jp, I)
-                rms[a, b] = float(np.sqrt(np.mean((I - judge_I) ** 2)) / judge_I.max())
+                rms[a, b] = float(np.sqrt(np.mean((I - ref_I) ** 2)) / ref_I.max())
         med = np.median(errs, axis=0)
         # smallest N from which on every larger N of the sweep also meets 1 cm^-1
         n1 = None
@@ -202,7 +202,7 @@ def learned_study(scivr, inputs, peaks, prob, judge_I, sizes, seeds, n_train, la
     ratio = np.array(plain["median_rel_rms"]) / np.array(learned["median_rel_rms"])
     return {
         "variance_ratio_plain_over_learned": float(np.median(ratio ** 2)),
-        "sizes": list(sizes), "seeds": list(seeds), "judge_peaks_cm1": [e * inputs.CM1_PER_HARTREE for e, _ in jp],
+        "sizes": list(sizes), "seeds": list(seeds), "ref_peaks_cm1": [e * inputs.CM1_PER_HARTREE for e, _ in jp],
         "plain": plain, "learned": learned,
         "flow": {"layers": layers, "width": width, "params": int(FLOW_PARAMS(prob.F, width, layers)),
                  "n_train": n_train, "epochs": epochs, "batch": batch, "lr": lr, "alpha": alpha,
@@ -232,8 +232,9 @@ def main():
                     help="only copy this many bytes device-to-device (counter calibration) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; the path shards by trajectory index "
-                                   "(see DESIGN.md) but no multi-GPU run is provided", "n_gpus": args.gpus}))
+        print(json.dumps({"error": "only one GPU is supported: the path shards by trajectory index (first_index "
+                                   "ranges) with one all-reduce of the K-vector, but no multi-GPU run is provided",
+                          "n_gpus": args.gpus}))
         sys.exit(2)
 
     import torch
@@ -349,7 +350,7 @@ def main():
                                                 seeds=(11, 12, 13, 14, 15),
                                                 n_train=65536, layers=4, width=128, epochs=20, batch=4096, lr=1e-3,
                                                 alpha=0.1)
-        out["learned_proposal"]["judge"] = (f"plain FP64 spectrum of the timed run: {args.steps} batches of {n} "
+        out["learned_proposal"]["reference"] = (f"plain FP64 spectrum of the timed run: {args.steps} batches of {n} "
                                             f"Husimi trajectories")
         lp = out["learned_proposal"]
         vp, vm = out["plain_fp64"]["value"], value

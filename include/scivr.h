@@ -52,7 +52,7 @@ typedef int32_t scivr_status;
 #define SCIVR_EDEVICE (-3)      /* a HIP call failed (sticky) */
 #define SCIVR_ESTATE (-4)       /* call out of order (e.g. propagate before initial conditions) */
 #define SCIVR_ENOGOOD (-5)      /* no good trajectory accumulated yet; spectrum zero-filled */
-#define SCIVR_EUNSUPPORTED (-6) /* valid request this build does not implement */
+#define SCIVR_EUNSUPPORTED (-6) /* valid request the library does not implement */
 
 #define SCIVR_PRECISION_FP64 0  /* every step in FP64 */
 #define SCIVR_PRECISION_MIXED 1 /* FP32 trajectory and Kahan action, FP64 monodromy/prefactor/branch, split-FP16 Fourier GEMM */

@@ -169,7 +169,7 @@ def uncoupled_morse(omega_cm1, *, x_e: float = 0.02, n_steps: int = 2048, dt: fl
                    omega=omega, name=name)
 
 
-# The workloads: sizes, grids and precision of each run (F=30 FP64 is the judge of the F=30 mixed run).
+# The workloads: sizes, grids and precision of each run (F=30 FP64 is the reference of the F=30 mixed run).
 WORKLOADS = {
     "F2_fp64": dict(F=2, n_traj=1024, n_steps=2048, dt=10.0, e_min=0.0, e_max=0.05, n_energies=512,
                     precision=PRECISION_FP64),

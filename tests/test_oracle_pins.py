@@ -448,7 +448,7 @@ def test_displaced_harmonic_spectrum_poisson_closed_form(oracle_mod):
             En = om[0] * (n0 + 0.5) + om[1] * (n1 + 0.5)
             wgt = h.poisson(n0, alpha2[0]) * h.poisson(n1, alpha2[1])
             ref += wgt * h.dirichlet_power(E, [En], prob.dt, prob.n_steps)[:, 0]
-    # Husimi weights make the estimator heavy-tailed for a displaced chi: judge the
+    # Husimi weights make the estimator heavy-tailed for a displaced chi: check the
     # total intensity against its own standard error from per-trajectory contributions
     dE = E[1] - E[0]
     scale = prob.dt ** 2 / (2 * math.pi * prob.total_time) * dE
