@@ -95,7 +95,24 @@ def cpu_baseline(prob, n_sample: int, seed: int):
                       f"{prob.n_energies} energies), {dt:.1f} s wall"}
 
 
-def run_form(scivr, torch, prob, n, steps, warmup, seed0=1000, chunk=0):
+def _energy_reader():
+    """A function returning the GPU's accumulated energy in joules (amdsmi), or None."""
+    try:
+        import amdsmi
+        amdsmi.amdsmi_init()
+        handle = amdsmi.amdsmi_get_processor_handles()[0]
+
+        def read():
+            e = amdsmi.amdsmi_get_energy_count(handle)
+            return e["energy_accumulator"] * e["counter_resolution"] * 1e-6
+        read()
+        return read
+    except Exception as exc:  # no SMI access on this machine
+        print(f"[bench] energy counter unavailable: {exc}", file=sys.stderr, flush=True)
+        return None
+
+
+def run_form(scivr, torch, prob, n, steps, warmup, seed0=1000, chunk=0, energy=None):
     """Time `steps` whole passes (sample + propagate + accumulate) of one form."""
     stream = torch.cuda.current_stream()
     ctx = scivr.Context(prob, max_traj=n)
@@ -119,16 +136,19 @@ def run_form(scivr, torch, prob, n, steps, warmup, seed0=1000, chunk=0):
     ctx.reset_spectrum(stream=stream)
     ctx.timing(True)
     torch.cuda.synchronize()
+    e0 = energy() if energy else None
     t0 = time.perf_counter()
     for i in range(steps):
         one_step(warmup + i)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    e1 = energy() if energy else None
     kt = ctx.kernel_times()
     I, n_good, n_total = ctx.read_spectrum()
     ctx.close()
     print(f"[bench] {prob.name}: {steps} steps in {wall:.3f} s; kernels {kt}", file=sys.stderr, flush=True)
-    return {"wall": wall, "kt": kt, "I": I, "n_good": n_good, "n_total": n_total}
+    joules = (e1 - e0) if (e0 is not None and e1 is not None) else None
+    return {"wall": wall, "kt": kt, "I": I, "n_good": n_good, "n_total": n_total, "joules": joules}
 
 
 def _peak_error_cm(peaks, inputs, E, T, ref_peaks, I):
@@ -212,6 +232,15 @@ def learned_study(scivr, inputs, peaks, prob, ref_I, sizes, seeds, n_train, laye
     }
 
 
+def _energy_summary(run, steps):
+    """GPU energy of one step (one batch) from the SMI accumulator, or None."""
+    if run.get("joules") is None:
+        return None
+    j = run["joules"] / steps
+    return {"J_per_step": j, "kWh_per_step": j / 3.6e6, "avg_W": run["joules"] / run["wall"],
+            "source": "amdsmi energy accumulator around the timed steps"}
+
+
 def FLOW_PARAMS(F, H, L):
     return L * (H * F + H + H * H + H + 2 * F * H + 2 * F)
 
@@ -256,11 +285,12 @@ def main():
         n = args.n_traj
     print(f"[bench] {args.workload}: F={prob.F} n={n} steps={prob.n_steps} K={prob.n_energies}", file=sys.stderr,
           flush=True)
-    main_run = run_form(scivr, torch, prob, n, args.steps, args.warmup, chunk=args.chunk)
+    energy = _energy_reader()
+    main_run = run_form(scivr, torch, prob, n, args.steps, args.warmup, chunk=args.chunk, energy=energy)
     plain = None
     if args.plain:
         pprob, _ = inputs.workload(args.plain)
-        plain = run_form(scivr, torch, pprob, n, args.steps, args.warmup, chunk=args.chunk)
+        plain = run_form(scivr, torch, pprob, n, args.steps, args.warmup, chunk=args.chunk, energy=energy)
 
     wall = main_run["wall"]
     kt = main_run["kt"]
@@ -322,6 +352,7 @@ def main():
             "launch_ms": fo_launch * 1e3,
         },
         "n_good_fraction": main_run["n_good"] / max(main_run["n_total"], 1),
+        "energy": _energy_summary(main_run, args.steps),
         "cpu_baseline": None,
     }
     if mixed:
@@ -340,6 +371,7 @@ def main():
             "fourier_ms": plain["kt"]["fourier"][1] / max(plain["kt"]["fourier"][0], 1),
             "speedup_of_value": value / pv,
             "n_good_fraction": plain["n_good"] / max(plain["n_total"], 1),
+            "energy": _energy_summary(plain, args.steps),
             "peak_error_cm1": worst * inputs.CM1_PER_HARTREE, "peaks_compared": len(pr), "peaks_missing": missing,
             "same_samples": True,
         }
@@ -362,6 +394,10 @@ def main():
             "mixed_learned_s": None if n_learn is None else n_learn * prob.n_steps / vm + train_s,
             "mixed_learned_training_s": train_s,
             "equal_variance_speedup": lp["variance_ratio_plain_over_learned"] * vm / vp,
+            "equal_variance_energy_ratio": (
+                None if not (out["energy"] and out["plain_fp64"]["energy"]) else
+                lp["variance_ratio_plain_over_learned"] * out["plain_fp64"]["energy"]["J_per_step"]
+                / out["energy"]["J_per_step"]),
             "note": ("plain: FP64 path with Husimi sampling; mixed_learned: mixed path with the learned proposal, "
                      "including its training batch and training time; equal_variance_speedup = (plain/learned "
                      "spectrum variance at equal N) x (mixed/plain throughput)"),

@@ -68,7 +68,7 @@ def test_flow_init_is_identity(scivr, oracle_mod):
     ctx.close()
 
 
-@pytest.mark.parametrize("F,H", [(3, 16), (9, 128)])
+@pytest.mark.parametrize("F,H", [(3, 16), (9, 128), (30, 256)])
 def test_flow_density_matches_oracle(scivr, oracle_mod, F, H):
     L = 4
     prob = inputs.morse_quartic(F, F, n_steps=8, n_energies=8)
@@ -88,13 +88,15 @@ def test_flow_density_matches_oracle(scivr, oracle_mod, F, H):
     lq16, u16 = fl.log_density(p0, q0, bf16=True)
     e16 = np.abs(lq16 - lq_o)
     _say(f"[flow F={F} H={H}] bf16 density: max |dlogq| {e16.max():.3e}, median {np.median(e16):.3e}")
-    # BF16 keeps 8 bits: relative 4e-3 per rounding, a few tens of s-values per point
-    assert np.median(e16) < 0.03 and e16.max() < 0.3
+    # BF16 keeps 8 bits (relative 4e-3 per rounding); log q sums F L log-scales whose
+    # rounding errors add up like a random walk
+    walk = math.sqrt(F * L)
+    assert np.median(e16) < 0.006 * walk and e16.max() < 0.06 * walk
     fl.close()
     ctx.close()
 
 
-@pytest.mark.parametrize("F,H,n", [(3, 16, 700), (9, 128, 2000)])
+@pytest.mark.parametrize("F,H,n", [(3, 16, 700), (9, 128, 2000), (30, 256, 1500)])
 def test_flow_gradient_matches_oracle(scivr, oracle_mod, F, H, n):
     L = 4
     prob = inputs.morse_quartic(F, F, n_steps=8, n_energies=8)
