@@ -74,17 +74,31 @@ __global__ void __launch_bounds__(256, 1) fourier_fp64_kernel(GemmArgs G)
             an[x] = Ap[x * 16];
             bn[x] = Bp[x * 16];
         }
+        // the four real products in four sweeps over the 16 blocks, so that the
+        // two updates of one accumulator are 16 independent MFMAs apart
+        double nai[4];
 #pragma unroll
-        for (int bi = 0; bi < 4; ++bi) {
-            const double ar = a[bi].x, ai = a[bi].y, nai = -a[bi].y;
+        for (int bi = 0; bi < 4; ++bi) nai[bi] = -a[bi].y;
 #pragma unroll
-            for (int bj = 0; bj < 4; ++bj) {
-                cr[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, b[bj].x, cr[bi][bj], 0, 0, 0);
-                cr[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(nai, b[bj].y, cr[bi][bj], 0, 0, 0);
-                ci[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, b[bj].y, ci[bi][bj], 0, 0, 0);
-                ci[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, b[bj].x, ci[bi][bj], 0, 0, 0);
-            }
-        }
+        for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+            for (int bj = 0; bj < 4; ++bj)
+                cr[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[bi].x, b[bj].x, cr[bi][bj], 0, 0, 0);
+#pragma unroll
+        for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+            for (int bj = 0; bj < 4; ++bj)
+                ci[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[bi].x, b[bj].y, ci[bi][bj], 0, 0, 0);
+#pragma unroll
+        for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+            for (int bj = 0; bj < 4; ++bj)
+                cr[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(nai[bi], b[bj].y, cr[bi][bj], 0, 0, 0);
+#pragma unroll
+        for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+            for (int bj = 0; bj < 4; ++bj)
+                ci[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[bi].y, b[bj].x, ci[bi][bj], 0, 0, 0);
 #pragma unroll
         for (int x = 0; x < 4; ++x) {
             a[x] = an[x];
