@@ -8,6 +8,11 @@ pointers may be given as torch tensors (their ``data_ptr``) or integers.
 The library must have been built (``python -m paper_1312_4698_amd.build``);
 importing this module on a machine without it raises immediately, there is no
 fallback path.
+
+PyTorch ships its own HIP runtime beside the system one the library links.
+When torch tensors or streams are passed in, initialise torch's GPU runtime
+(``torch.cuda.init()`` or any torch GPU call) before the first library call:
+the two runtimes share the device in that order.
 """
 from __future__ import annotations
 

@@ -13,6 +13,19 @@ def pytest_configure(config):
     config.addinivalue_line("markers", "slow: longer CPU test")
 
 
+def pytest_collection_modifyitems(session, config, items):
+    # torch ships its own HIP runtime next to the system one that the library
+    # links; the two share the device when torch's initialises first, so GPU
+    # runs set it up before any library call (as bench.py and the smoke check do)
+    if any(item.get_closest_marker("gpu") for item in items):
+        try:
+            import torch
+            if torch.cuda.is_available():
+                torch.cuda.init()
+        except Exception:
+            pass
+
+
 @pytest.fixture(scope="session")
 def oracle_mod():
     from oracle import oracle as O
