@@ -1,4 +1,5 @@
-// FP64 trajectory kernel of the TA-SC-IVR spectrum for gfx950.
+// Trajectory kernel of the TA-SC-IVR spectrum for gfx950, F <= 16, in the FP64
+// and the mixed-precision form.
 //
 // One trajectory is owned by a group of F lanes of a wave64 (floor(64/F)
 // trajectories per wave).  Lane c owns degree of freedom c:
@@ -29,7 +30,8 @@
 // e^{i dt sum gamma}; phi = (theta - t sum gamma)/2 (the separable
 // approximation after Eq. (9)).  Each step writes the amplitude
 // <chi|p_t,q_t> e^{i (S_t + phi_t)} (zero once the trajectory is flagged) into
-// a time-major [t][trajectory] matrix, the left operand of the Fourier GEMM.
+// the left operand of the Fourier GEMM: a time-major [t][trajectory] FP64
+// matrix, or in the mixed form FP16 hi/lo planes [t / 8][trajectory][t % 8].
 #include <math.h>
 
 #include <type_traits>
@@ -60,7 +62,11 @@ struct alignas(16) GroupLds {
 // (|a_k|, 63 - pos) keys of the live rows (ties go to the lowest position, as
 // in a row-swapping LU); the lane holding the winner publishes that row; live
 // rows read it back and eliminate.  The row at position k and the pivot swap
-// positions, and the determinant changes sign when they differ.
+// positions, and the determinant changes sign when they differ.  Lookahead:
+// each step updates column k + 1 first and sends the pivot search of step
+// k + 1 off before eliminating the rest of the row, so the search's LDS round
+// trip overlaps that arithmetic (every element sees the same operations in
+// the same order as without it).
 template <int N>
 __device__ inline double lu_det_real2(double (&a0)[N], double (&a1)[N], int pos0, int pos1, double *piv,
                                       unsigned long long *slot)
@@ -69,18 +75,20 @@ __device__ inline double lu_det_real2(double (&a0)[N], double (&a1)[N], int pos0
     slot[pos0] = 0ull;
     slot[pos1] = 0ull;
     double det = 1.0;
+    unsigned long long win;
+    {
+        const unsigned long long k0 = pivot_key(fabs(a0[0]), pos0), k1 = pivot_key(fabs(a1[0]), pos1);
+        lds_order();
+        atomicMax(&slot[0], k0 > k1 ? k0 : k1);
+        lds_order();
+        win = __hip_atomic_load(&slot[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+    }
 #pragma unroll
     for (int k = 0; k < N; ++k) {
-        const unsigned long long k0 = alive0 ? pivot_key(fabs(a0[k]), pos0) : 0ull;
-        const unsigned long long k1 = alive1 ? pivot_key(fabs(a1[k]), pos1) : 0ull;
-        const unsigned long long kk = k0 > k1 ? k0 : k1;
-        lds_order();
-        if (kk) atomicMax(&slot[k], kk);
-        lds_order();
-        const unsigned long long win = __hip_atomic_load(&slot[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
         const int ppos = 63 - (int)(win & 63ull);
         const bool isp0 = alive0 && pos0 == ppos;
         const bool isp1 = alive1 && pos1 == ppos;
+        lds_order();
         if (isp0) {
 #pragma unroll
             for (int jj = k; jj < N; ++jj) piv[jj] = a0[jj];
@@ -96,15 +104,25 @@ __device__ inline double lu_det_real2(double (&a0)[N], double (&a1)[N], int pos0
         pos1 = (alive1 && pos1 == k) ? ppos : pos1;
         alive0 = alive0 && !isp0;
         alive1 = alive1 && !isp1;
-        if (alive0 || alive1) {  // lanes whose rows are all eliminated skip the broadcast read
+        if (k + 1 < N) {
             const double inv = rcp_nr(pk);
             const double l0 = alive0 ? a0[k] * inv : 0.0;
             const double l1 = alive1 ? a1[k] * inv : 0.0;
+            const double v = piv[k + 1];
+            a0[k + 1] = fma(-l0, v, a0[k + 1]);
+            a1[k + 1] = fma(-l1, v, a1[k + 1]);
+            const unsigned long long k0 = alive0 ? pivot_key(fabs(a0[k + 1]), pos0) : 0ull;
+            const unsigned long long k1 = alive1 ? pivot_key(fabs(a1[k + 1]), pos1) : 0ull;
+            const unsigned long long kk = k0 > k1 ? k0 : k1;
+            lds_order();
+            if (kk) atomicMax(&slot[k + 1], kk);
+            lds_order();
+            win = __hip_atomic_load(&slot[k + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
 #pragma unroll
-            for (int jj = k + 1; jj < N; ++jj) {
-                const double v = piv[jj];
-                a0[jj] = fma(-l0, v, a0[jj]);
-                a1[jj] = fma(-l1, v, a1[jj]);
+            for (int jj = k + 2; jj < N; ++jj) {
+                const double w = piv[jj];
+                a0[jj] = fma(-l0, w, a0[jj]);
+                a1[jj] = fma(-l1, w, a1[jj]);
             }
         }
     }
@@ -113,7 +131,8 @@ __device__ inline double lu_det_real2(double (&a0)[N], double (&a1)[N], int pos0
 }
 
 // det of the complex N x N matrix (N = F) whose row `pos` lives in (ar, ai);
-// pivot on |a_k|^2; the pivot row is published interleaved (re, im).
+// pivot on |a_k|^2; the pivot row is published interleaved (re, im).  Same
+// lookahead as the real elimination.
 template <int N>
 __device__ inline void lu_det_complex(double (&ar)[N], double (&ai)[N], int pos, double *piv,
                                       unsigned long long *slot, double &dr, double &di)
@@ -121,15 +140,19 @@ __device__ inline void lu_det_complex(double (&ar)[N], double (&ai)[N], int pos,
     bool alive = true;
     slot[pos] = 0ull;
     double zr = 1.0, zi = 0.0;
+    unsigned long long win;
+    {
+        const double m2 = fma(ar[0], ar[0], ai[0] * ai[0]);
+        lds_order();
+        atomicMax(&slot[0], pivot_key(m2, pos));
+        lds_order();
+        win = __hip_atomic_load(&slot[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+    }
 #pragma unroll
     for (int k = 0; k < N; ++k) {
-        const double m2 = fma(ar[k], ar[k], ai[k] * ai[k]);
-        lds_order();
-        if (alive) atomicMax(&slot[k], pivot_key(m2, pos));
-        lds_order();
-        const unsigned long long win = __hip_atomic_load(&slot[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
         const int ppos = 63 - (int)(win & 63ull);
         const bool isp = alive && pos == ppos;
+        lds_order();
         if (isp) {
 #pragma unroll
             for (int jj = k; jj < N; ++jj) {
@@ -145,12 +168,22 @@ __device__ inline void lu_det_complex(double (&ar)[N], double (&ai)[N], int pos,
         zi = (ppos != k) ? -ni : ni;
         pos = (alive && pos == k) ? ppos : pos;
         alive = alive && !isp;
-        if (alive) {
+        if (k + 1 < N) {
             const double inv = rcp_nr(fma(pr, pr, pi * pi));
-            const double lr = (ar[k] * pr + ai[k] * pi) * inv;
-            const double li = (ai[k] * pr - ar[k] * pi) * inv;
+            const double lr = alive ? (ar[k] * pr + ai[k] * pi) * inv : 0.0;
+            const double li = alive ? (ai[k] * pr - ar[k] * pi) * inv : 0.0;
+            {
+                const double br = piv[2 * (k + 1)], bi = piv[2 * (k + 1) + 1];
+                ar[k + 1] = ar[k + 1] - (lr * br - li * bi);
+                ai[k + 1] = ai[k + 1] - (lr * bi + li * br);
+            }
+            const double m2 = fma(ar[k + 1], ar[k + 1], ai[k + 1] * ai[k + 1]);
+            lds_order();
+            if (alive) atomicMax(&slot[k + 1], pivot_key(m2, pos));
+            lds_order();
+            win = __hip_atomic_load(&slot[k + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
 #pragma unroll
-            for (int jj = k + 1; jj < N; ++jj) {
+            for (int jj = k + 2; jj < N; ++jj) {
                 const double br = piv[2 * jj], bi = piv[2 * jj + 1];
                 ar[jj] = ar[jj] - (lr * br - li * bi);
                 ai[jj] = ai[jj] - (lr * bi + li * br);
