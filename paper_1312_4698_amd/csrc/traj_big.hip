@@ -105,9 +105,11 @@ __device__ __attribute__((always_inline)) inline double lu_det_rows(double (&a)[
 {
     bool alive = active;
     double det = 1.0;
+    // lookahead: column k + 1 is updated first and its pivot search runs
+    // while the rest of the row is eliminated
+    unsigned long long win = wave_max_u64(alive ? pivot_key(fabs(a[0]), pos) : 0ull);
 #pragma unroll
     for (int k = 0; k < N; ++k) {
-        const unsigned long long win = wave_max_u64(alive ? pivot_key(fabs(a[k]), pos) : 0ull);
         const int ppos = 63 - (int)(win & 63ull);
         const int pl = pivot_lane(alive, pos, ppos);
         const bool isp = alive && pos == ppos;
@@ -115,9 +117,13 @@ __device__ __attribute__((always_inline)) inline double lu_det_rows(double (&a)[
         det *= (ppos != k) ? -pk : pk;
         pos = (alive && pos == k) ? ppos : pos;
         alive = alive && !isp;
-        const double l = alive ? a[k] * rcp_nr(pk) : 0.0;
+        if (k + 1 < N) {
+            const double l = alive ? a[k] * rcp_nr(pk) : 0.0;
+            a[k + 1] = fma(-l, readlane_f64(a[k + 1], pl), a[k + 1]);
+            win = wave_max_u64(alive ? pivot_key(fabs(a[k + 1]), pos) : 0ull);
 #pragma unroll
-        for (int jj = k + 1; jj < N; ++jj) a[jj] = fma(-l, readlane_f64(a[jj], pl), a[jj]);
+            for (int jj = k + 2; jj < N; ++jj) a[jj] = fma(-l, readlane_f64(a[jj], pl), a[jj]);
+        }
     }
     return det;
 }
@@ -131,10 +137,9 @@ __device__ __attribute__((always_inline)) inline void lu_det_rows_complex(double
 {
     bool alive = active;
     double zr = 1.0, zi = 0.0;
+    unsigned long long win = wave_max_u64(alive ? pivot_key(fma(ar[0], ar[0], ai[0] * ai[0]), pos) : 0ull);
 #pragma unroll
     for (int k = 0; k < N; ++k) {
-        const double m2 = fma(ar[k], ar[k], ai[k] * ai[k]);
-        const unsigned long long win = wave_max_u64(alive ? pivot_key(m2, pos) : 0ull);
         const int ppos = 63 - (int)(win & 63ull);
         const int pl = pivot_lane(alive, pos, ppos);
         const bool isp = alive && pos == ppos;
@@ -145,14 +150,22 @@ __device__ __attribute__((always_inline)) inline void lu_det_rows_complex(double
         zi = (ppos != k) ? -ni : ni;
         pos = (alive && pos == k) ? ppos : pos;
         alive = alive && !isp;
-        const double inv = rcp_nr(fma(pr, pr, pi * pi));
-        const double lr = alive ? (ar[k] * pr + ai[k] * pi) * inv : 0.0;
-        const double li = alive ? (ai[k] * pr - ar[k] * pi) * inv : 0.0;
+        if (k + 1 < N) {
+            const double inv = rcp_nr(fma(pr, pr, pi * pi));
+            const double lr = alive ? (ar[k] * pr + ai[k] * pi) * inv : 0.0;
+            const double li = alive ? (ai[k] * pr - ar[k] * pi) * inv : 0.0;
+            {
+                const double br = readlane_f64(ar[k + 1], pl), bi = readlane_f64(ai[k + 1], pl);
+                ar[k + 1] = ar[k + 1] - (lr * br - li * bi);
+                ai[k + 1] = ai[k + 1] - (lr * bi + li * br);
+            }
+            win = wave_max_u64(alive ? pivot_key(fma(ar[k + 1], ar[k + 1], ai[k + 1] * ai[k + 1]), pos) : 0ull);
 #pragma unroll
-        for (int jj = k + 1; jj < N; ++jj) {
-            const double br = readlane_f64(ar[jj], pl), bi = readlane_f64(ai[jj], pl);
-            ar[jj] = ar[jj] - (lr * br - li * bi);
-            ai[jj] = ai[jj] - (lr * bi + li * br);
+            for (int jj = k + 2; jj < N; ++jj) {
+                const double br = readlane_f64(ar[jj], pl), bi = readlane_f64(ai[jj], pl);
+                ar[jj] = ar[jj] - (lr * br - li * bi);
+                ai[jj] = ai[jj] - (lr * bi + li * br);
+            }
         }
     }
     dr = zr;
