@@ -217,6 +217,12 @@ traj_kernel(TrajArgs A, const ProblemDev *__restrict__ P0)
     __shared__ double lam_lds[F * F];  // coupling matrix, shared by the wave's groups
     __shared__ R qv_all[TPW][F + (F & 1)], pm_all[TPW][F + (F & 1)];
     __shared__ R pg_all[TPW][F + (F & 1)], ph_all[TPW][F + (F & 1)], pv_all[TPW][F + (F & 1)];
+    // The p halves of the lane's two monodromy columns wait in LDS while the
+    // eliminations run where the register file cannot hold them, the rows of
+    // M^T and the pivot traffic at once (F <= 6, three or four waves per SIMD;
+    // at two waves per SIMD the LDS round trip costs more than it saves).
+    constexpr bool STASH = F <= 6;
+    __shared__ double stash_all[STASH ? TPW : 1][2][F][F];
 
     const int lane = threadIdx.x;
     const ProblemDev *__restrict__ P = P0;
@@ -433,6 +439,13 @@ traj_kernel(TrajArgs A, const ProblemDev *__restrict__ P0)
                 are[i] = 0.5 * (si * dqQ[i] * isgc + dpP[i] * sgc * isi);
                 aim[i] = 0.5 * (-si * dqP[i] * sgc + dpQ[i] * isi * isgc);
             }
+            if constexpr (STASH) {
+#pragma unroll
+                for (int i = 0; i < F; ++i) {
+                    stash_all[grp][0][i][c] = dpP[i];
+                    stash_all[grp][1][i][c] = dpQ[i];
+                }
+            }
             lu_det_complex<F>(are, aim, c, L.pivA, L.slotA, dAr, dAi);
         }
 
@@ -442,9 +455,9 @@ traj_kernel(TrajArgs A, const ProblemDev *__restrict__ P0)
             double r0[N2], r1[N2];  // rows c and F + c of M^T, entries ordered (p rows, q rows) of M
 #pragma unroll
             for (int i = 0; i < F; ++i) {
-                r0[i] = dpP[i];
+                r0[i] = STASH ? stash_all[STASH ? grp : 0][0][i][c] : dpP[i];
                 r0[F + i] = dqP[i];
-                r1[i] = dpQ[i];
+                r1[i] = STASH ? stash_all[STASH ? grp : 0][1][i][c] : dpQ[i];
                 r1[F + i] = dqQ[i];
             }
             const double dM = lu_det_real2<N2>(r0, r1, c, F + c, L.pivM, L.slotM);
@@ -452,6 +465,14 @@ traj_kernel(TrajArgs A, const ProblemDev *__restrict__ P0)
             detM = dM;
             if (!(dev <= maxdev)) maxdev = dev;
             if (!(dev <= Ps->det_tol)) good = false;
+        }
+        if constexpr (STASH) {
+#pragma unroll
+            for (int i = 0; i < F; ++i) {
+                dpP[i] = stash_all[grp][0][i][c];
+                dpQ[i] = stash_all[grp][1][i][c];
+            }
+            lds_order();
         }
 
         // continuous branch: theta accumulates the principal argument of
