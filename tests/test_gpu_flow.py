@@ -273,3 +273,57 @@ def test_learned_proposal_spectrum_matches_plain(scivr):
     assert rel < 0.05
     fl.close()
     ctx.close()
+
+
+def _ratio_estimate(prob, ctx):
+    """Integrated spectrum of the last batch as the ratio estimator
+    sum_j c_j / sum_j good_j r_j (r_j = Husimi density / sampling density),
+    with its delta-method standard error."""
+    c = ctx.read_contributions()
+    p0, q0, lr = ctx.read_initial()
+    good = ctx.read_state()["good"].astype(bool)
+    g = np.asarray(prob.gamma)[:, None]
+    log_h = (-len(prob.gamma) * np.log(2.0 * np.pi)
+             - 0.5 * np.sum(g * (q0 - np.asarray(prob.q_eq)[:, None]) ** 2
+                            + (p0 - np.asarray(prob.p_eq)[:, None]) ** 2 / g, axis=0))
+    r = np.where(good, np.exp(log_h - lr), 0.0)
+    x = c.sum() / r.sum()
+    n = len(c)
+    se = np.std(c - x * r) / (np.sqrt(n) * r.mean())
+    return x, se
+
+
+def test_mixed_learned_pipeline_at_f30(scivr):
+    """The F = 30 form end to end at reduced length: mixed-precision batch,
+    a width-256 flow trained on its contributions, a mixture batch, and its
+    spectrum.  Two independent Monte Carlo estimates are compared where their
+    statistics are known: the integrated spectrum, within five standard errors."""
+    prob = inputs.morse_quartic(30, 30, n_steps=200, n_energies=256, e_max=0.25,
+                                precision=inputs.PRECISION_MIXED)
+    n = 4096
+    ctx = scivr.Context(prob, max_traj=n)
+    ctx.run(seed=5, n_traj=n)
+    I_h, ng_h, _ = ctx.read_spectrum()
+    x_h, se_h = _ratio_estimate(prob, ctx)
+    fl = scivr.Flow(ctx, 4, 256, seed=9)
+    assert fl.n_params == 356592
+    loss = fl.train_on_batch(epochs=5, batch=1024, lr=1e-3)
+    ctx.reset_spectrum()
+    ess, used = fl.sample(seed=6, n_traj=n, alpha=0.1)
+    ctx.propagate()
+    ctx.accumulate()
+    I_l, ng_l, nt = ctx.read_spectrum()
+    x_l, se_l = _ratio_estimate(prob, ctx)
+    z = (x_l - x_h) / np.hypot(se_h, se_l)
+    # the spectrum sums to the ratio estimate times one constant in both batches
+    k_h, k_l = I_h.sum() / x_h, I_l.sum() / x_l
+    rel = np.max(np.abs(I_l - I_h)) / I_h.max()
+    _say(f"[flow F=30] loss {loss:.3f} ess {ess:.3f} used {used} good {ng_h}/{ng_l}; "
+         f"integrated {x_h:.4e}+-{se_h:.1e} vs {x_l:.4e}+-{se_l:.1e} (z {z:.2f}); max rel diff {rel:.3e}")
+    assert np.isfinite(loss) and used and ess > 0.1
+    assert ng_l > 0.5 * nt and np.all(np.isfinite(I_l))
+    assert abs(k_l / k_h - 1.0) < 1e-9
+    assert abs(z) < 5.0
+    assert rel < 0.3
+    fl.close()
+    ctx.close()
