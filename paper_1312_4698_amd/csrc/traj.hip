@@ -14,9 +14,9 @@
 //    whose rows are the columns lane c already holds: column c of A (one row of
 //    A^T per lane) and columns c, F + c of M (two rows of M^T per lane), so
 //    no transpose is needed.  Gaussian elimination with partial pivoting runs
-//    across the group's lanes: one LDS atomic max over packed (|a|, position)
-//    keys picks each pivot, the pivot lane publishes its row, the live rows
-//    read it back as a broadcast.
+//    across the group's lanes: each lane publishes one packed (|a|, position)
+//    key, every lane reads the group's keys back and takes their maximum, the
+//    pivot lane publishes its row, the live rows read it back as a broadcast.
 //
 // The fourth-order symplectic step is the drift-kick-drift triple jump
 // (Yoshida / Forest-Ruth); each kick evaluates gradient, Hessian and potential
@@ -45,47 +45,71 @@ namespace {
 template <int F>
 struct alignas(16) GroupLds {
     static constexpr int N2 = 2 * F;
+    static constexpr int KS = (F + 3) & ~3;
     // bytes of the fields below; the padding makes the stride between groups
     // 16 B more than a multiple of the 256-byte bank row, so the groups'
     // simultaneous broadcast reads fall into different banks
-    static constexpr int BYTES = 8 * (3 * N2 + F + (F & 1));
+    static constexpr int BYTES = 8 * 2 * N2 + 4 * KS;
     static constexpr int PAD = ((16 - BYTES % 256) % 256 + 256) % 256 / 8;
     double pivM[N2];                   // pivot row of the real elimination
     double pivA[N2];                   // pivot row of the complex elimination (re, im interleaved)
-    unsigned long long slotM[N2];      // per-step argmax keys of the two eliminations
-    unsigned long long slotA[F + (F & 1)];
+    unsigned keys[KS];                 // one pivot key per lane of the group
     double pad[PAD > 0 ? PAD : 2];
 };
 
-// det of the real N x N matrix (N = 2F) whose rows at positions pos0, pos1
-// live in lane-local a0[], a1[].  Each step: LDS atomic max over packed
-// (|a_k|, 63 - pos) keys of the live rows (ties go to the lowest position, as
-// in a row-swapping LU); the lane holding the winner publishes that row; live
+// Pivot search of one elimination step: lane `lane` of the group of G lanes
+// publishes its best key, and every lane reads the G keys back (16-byte
+// broadcast reads) and takes their maximum.  The slots are rewritten at the
+// next step; the wave's LDS instructions run in order, so this step's reads
+// complete before any lane's next write.
+template <int G>
+__device__ inline unsigned group_max_key(unsigned *keys, int lane, unsigned mine)
+{
+    lds_order();
+    keys[lane] = mine;
+    lds_order();
+    constexpr int NQ = (G + 3) / 4;
+    unsigned v[4 * NQ];
+#pragma unroll
+    for (int qd = 0; qd < NQ; ++qd) {
+        const uint4 t = reinterpret_cast<const uint4 *>(keys)[qd];
+        v[4 * qd] = t.x;
+        v[4 * qd + 1] = t.y;
+        v[4 * qd + 2] = t.z;
+        v[4 * qd + 3] = t.w;
+    }
+    unsigned m = v[0];
+    int i = 1;
+#pragma unroll
+    for (; i + 1 < G; i += 2) m = max(m, max(v[i], v[i + 1]));
+    if (i < G) m = max(m, v[i]);
+    return m;
+}
+
+// det of the real N x N matrix (N = 2G) whose rows at positions pos0, pos1
+// live in lane-local a0[], a1[] of lane `lane` of a group of G lanes.  Each
+// step picks the pivot as the largest key (group_max_key) of the live rows'
+// entries in column k; the lane holding the winner publishes that row; live
 // rows read it back and eliminate.  The row at position k and the pivot swap
 // positions, and the determinant changes sign when they differ.  Lookahead:
 // each step updates column k + 1 first and sends the pivot search of step
 // k + 1 off before eliminating the rest of the row, so the search's LDS round
 // trip overlaps that arithmetic (every element sees the same operations in
 // the same order as without it).
-template <int N>
-__device__ inline double lu_det_real2(double (&a0)[N], double (&a1)[N], int pos0, int pos1, double *piv,
-                                      unsigned long long *slot)
+template <int N, int G>
+__device__ inline double lu_det_real2(double (&a0)[N], double (&a1)[N], int pos0, int pos1, int lane, double *piv,
+                                      unsigned *keys)
 {
     bool alive0 = true, alive1 = true;
-    slot[pos0] = 0ull;
-    slot[pos1] = 0ull;
     double det = 1.0;
-    unsigned long long win;
+    unsigned win;
     {
-        const unsigned long long k0 = pivot_key(fabs(a0[0]), pos0), k1 = pivot_key(fabs(a1[0]), pos1);
-        lds_order();
-        atomicMax(&slot[0], k0 > k1 ? k0 : k1);
-        lds_order();
-        win = __hip_atomic_load(&slot[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+        const unsigned k0 = pivot_key32(fabs(a0[0]), pos0), k1 = pivot_key32(fabs(a1[0]), pos1);
+        win = group_max_key<G>(keys, lane, max(k0, k1));
     }
 #pragma unroll
     for (int k = 0; k < N; ++k) {
-        const int ppos = 63 - (int)(win & 63ull);
+        const int ppos = 63 - (int)(win & 63u);
         const bool isp0 = alive0 && pos0 == ppos;
         const bool isp1 = alive1 && pos1 == ppos;
         lds_order();
@@ -111,13 +135,9 @@ __device__ inline double lu_det_real2(double (&a0)[N], double (&a1)[N], int pos0
             const double v = piv[k + 1];
             a0[k + 1] = fma(-l0, v, a0[k + 1]);
             a1[k + 1] = fma(-l1, v, a1[k + 1]);
-            const unsigned long long k0 = alive0 ? pivot_key(fabs(a0[k + 1]), pos0) : 0ull;
-            const unsigned long long k1 = alive1 ? pivot_key(fabs(a1[k + 1]), pos1) : 0ull;
-            const unsigned long long kk = k0 > k1 ? k0 : k1;
-            lds_order();
-            if (kk) atomicMax(&slot[k + 1], kk);
-            lds_order();
-            win = __hip_atomic_load(&slot[k + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+            const unsigned k0 = alive0 ? pivot_key32(fabs(a0[k + 1]), pos0) : 0u;
+            const unsigned k1 = alive1 ? pivot_key32(fabs(a1[k + 1]), pos1) : 0u;
+            win = group_max_key<G>(keys, lane, max(k0, k1));
 #pragma unroll
             for (int jj = k + 2; jj < N; ++jj) {
                 const double w = piv[jj];
@@ -130,27 +150,19 @@ __device__ inline double lu_det_real2(double (&a0)[N], double (&a1)[N], int pos0
     return det;
 }
 
-// det of the complex N x N matrix (N = F) whose row `pos` lives in (ar, ai);
-// pivot on |a_k|^2; the pivot row is published interleaved (re, im).  Same
-// lookahead as the real elimination.
+// det of the complex N x N matrix (N = G) whose row `pos` lives in (ar, ai) of
+// lane `lane`; pivot on |a_k|^2; the pivot row is published interleaved (re,
+// im).  Same pivot search and lookahead as the real elimination.
 template <int N>
-__device__ inline void lu_det_complex(double (&ar)[N], double (&ai)[N], int pos, double *piv,
-                                      unsigned long long *slot, double &dr, double &di)
+__device__ inline void lu_det_complex(double (&ar)[N], double (&ai)[N], int pos, int lane, double *piv,
+                                      unsigned *keys, double &dr, double &di)
 {
     bool alive = true;
-    slot[pos] = 0ull;
     double zr = 1.0, zi = 0.0;
-    unsigned long long win;
-    {
-        const double m2 = fma(ar[0], ar[0], ai[0] * ai[0]);
-        lds_order();
-        atomicMax(&slot[0], pivot_key(m2, pos));
-        lds_order();
-        win = __hip_atomic_load(&slot[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
-    }
+    unsigned win = group_max_key<N>(keys, lane, pivot_key32(fma(ar[0], ar[0], ai[0] * ai[0]), pos));
 #pragma unroll
     for (int k = 0; k < N; ++k) {
-        const int ppos = 63 - (int)(win & 63ull);
+        const int ppos = 63 - (int)(win & 63u);
         const bool isp = alive && pos == ppos;
         lds_order();
         if (isp) {
@@ -178,10 +190,7 @@ __device__ inline void lu_det_complex(double (&ar)[N], double (&ai)[N], int pos,
                 ai[k + 1] = ai[k + 1] - (lr * bi + li * br);
             }
             const double m2 = fma(ar[k + 1], ar[k + 1], ai[k + 1] * ai[k + 1]);
-            lds_order();
-            if (alive) atomicMax(&slot[k + 1], pivot_key(m2, pos));
-            lds_order();
-            win = __hip_atomic_load(&slot[k + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+            win = group_max_key<N>(keys, lane, alive ? pivot_key32(m2, pos) : 0u);
 #pragma unroll
             for (int jj = k + 2; jj < N; ++jj) {
                 const double br = piv[2 * jj], bi = piv[2 * jj + 1];
@@ -446,7 +455,7 @@ traj_kernel(TrajArgs A, const ProblemDev *__restrict__ P0)
                     stash_all[grp][1][i][c] = dpQ[i];
                 }
             }
-            lu_det_complex<F>(are, aim, c, L.pivA, L.slotA, dAr, dAi);
+            lu_det_complex<F>(are, aim, c, c, L.pivA, L.keys, dAr, dAi);
         }
 
         // stability monitor |det(M)^2 - 1| on checked steps
@@ -460,7 +469,7 @@ traj_kernel(TrajArgs A, const ProblemDev *__restrict__ P0)
                 r1[i] = STASH ? stash_all[STASH ? grp : 0][1][i][c] : dpQ[i];
                 r1[F + i] = dqQ[i];
             }
-            const double dM = lu_det_real2<N2>(r0, r1, c, F + c, L.pivM, L.slotM);
+            const double dM = lu_det_real2<N2, F>(r0, r1, c, F + c, c, L.pivM, L.keys);
             const double dev = fabs(dM * dM - 1.0);
             detM = dM;
             if (!(dev <= maxdev)) maxdev = dev;

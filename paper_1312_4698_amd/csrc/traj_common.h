@@ -37,6 +37,16 @@ __device__ inline unsigned long long pivot_key(double mag, int pos)
     return (dbits(mag) & ~63ull) | (unsigned long long)(63 - pos);
 }
 
+// 32-bit pivot key: the high word of the (non-negative) magnitude's bits with
+// its low six bits replaced by 63 - pos.  Keys order as the magnitudes
+// truncated to 14 mantissa bits, ties going to the lowest position (partial
+// pivoting up to a factor 1 + 2^-14 in the pivot's size); 0 marks a row that
+// is no longer a candidate.
+__device__ inline unsigned pivot_key32(double mag, int pos)
+{
+    return ((unsigned)(dbits(mag) >> 32) & ~63u) | (unsigned)(63 - pos);
+}
+
 // Kahan-compensated running sum (used for the FP32 action of the mixed form).
 struct Kahan {
     float s = 0.f, c = 0.f;
