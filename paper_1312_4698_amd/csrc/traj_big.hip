@@ -52,20 +52,13 @@ struct alignas(16) BigLds {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 
-// Largest 64-bit key over the wave (every lane gets it).  DPP row shifts
+// Largest 32-bit key over the wave (every lane gets it).  DPP row shifts
 // 1, 2, 4, 8 leave each row's maximum in its lane 15, row broadcasts 15 and 31
 // carry it to lane 63; lanes without a source take the identity 0.
-__device__ __attribute__((always_inline)) inline unsigned long long wave_max_u64(unsigned long long v)
+__device__ __attribute__((always_inline)) inline unsigned wave_max_u32(unsigned v)
 {
-    unsigned lo = (unsigned)v, hi = (unsigned)(v >> 32);
-#define SCIVR_DPP_MAX(ctrl, rmask)                                                                    \
-    {                                                                                                 \
-        const unsigned olo = (unsigned)__builtin_amdgcn_update_dpp(0, (int)lo, ctrl, rmask, 0xf, false); \
-        const unsigned ohi = (unsigned)__builtin_amdgcn_update_dpp(0, (int)hi, ctrl, rmask, 0xf, false); \
-        const bool gt = ohi > hi || (ohi == hi && olo > lo);                                          \
-        lo = gt ? olo : lo;                                                                           \
-        hi = gt ? ohi : hi;                                                                           \
-    }
+#define SCIVR_DPP_MAX(ctrl, rmask) \
+    v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, ctrl, rmask, 0xf, false));
     SCIVR_DPP_MAX(0x111, 0xf)  // row_shr:1
     SCIVR_DPP_MAX(0x112, 0xf)  // row_shr:2
     SCIVR_DPP_MAX(0x114, 0xf)  // row_shr:4
@@ -73,9 +66,7 @@ __device__ __attribute__((always_inline)) inline unsigned long long wave_max_u64
     SCIVR_DPP_MAX(0x142, 0xa)  // row_bcast:15 into rows 1 and 3
     SCIVR_DPP_MAX(0x143, 0xc)  // row_bcast:31 into rows 2 and 3
 #undef SCIVR_DPP_MAX
-    lo = (unsigned)__builtin_amdgcn_readlane((int)lo, 63);
-    hi = (unsigned)__builtin_amdgcn_readlane((int)hi, 63);
-    return ((unsigned long long)hi << 32) | lo;
+    return (unsigned)__builtin_amdgcn_readlane((int)v, 63);
 }
 
 // The value of v in lane l (l uniform across the wave), into scalar registers.
@@ -95,8 +86,8 @@ __device__ __attribute__((always_inline)) inline int pivot_lane(bool alive, int 
 
 // det of the real N x N matrix whose row `pos` lives in a[] of the lanes with
 // `active` set (positions 0..N-1, one row per lane of the wave).  The pivot of
-// each column is the live row with the largest |a_k| (ties to the lowest
-// position, as in a row-swapping LU), found by a wave-wide maximum; its row is
+// each column is the live row with the largest |a_k| (compared as 32-bit keys,
+// ties to the lowest position), found by a wave-wide maximum; its row is
 // read into scalar registers lane by lane, so the elimination needs no LDS.
 // The row at position k and the pivot swap positions; the determinant
 // changes sign when they differ.  Every lane returns det.
@@ -107,10 +98,10 @@ __device__ __attribute__((always_inline)) inline double lu_det_rows(double (&a)[
     double det = 1.0;
     // lookahead: column k + 1 is updated first and its pivot search runs
     // while the rest of the row is eliminated
-    unsigned long long win = wave_max_u64(alive ? pivot_key(fabs(a[0]), pos) : 0ull);
+    unsigned win = wave_max_u32(alive ? pivot_key32(fabs(a[0]), pos) : 0u);
 #pragma unroll
     for (int k = 0; k < N; ++k) {
-        const int ppos = 63 - (int)(win & 63ull);
+        const int ppos = 63 - (int)(win & 63u);
         const int pl = pivot_lane(alive, pos, ppos);
         const bool isp = alive && pos == ppos;
         const double pk = readlane_f64(a[k], pl);
@@ -120,7 +111,7 @@ __device__ __attribute__((always_inline)) inline double lu_det_rows(double (&a)[
         if (k + 1 < N) {
             const double l = alive ? a[k] * rcp_nr(pk) : 0.0;
             a[k + 1] = fma(-l, readlane_f64(a[k + 1], pl), a[k + 1]);
-            win = wave_max_u64(alive ? pivot_key(fabs(a[k + 1]), pos) : 0ull);
+            win = wave_max_u32(alive ? pivot_key32(fabs(a[k + 1]), pos) : 0u);
 #pragma unroll
             for (int jj = k + 2; jj < N; ++jj) a[jj] = fma(-l, readlane_f64(a[jj], pl), a[jj]);
         }
@@ -137,10 +128,10 @@ __device__ __attribute__((always_inline)) inline void lu_det_rows_complex(double
 {
     bool alive = active;
     double zr = 1.0, zi = 0.0;
-    unsigned long long win = wave_max_u64(alive ? pivot_key(fma(ar[0], ar[0], ai[0] * ai[0]), pos) : 0ull);
+    unsigned win = wave_max_u32(alive ? pivot_key32(fma(ar[0], ar[0], ai[0] * ai[0]), pos) : 0u);
 #pragma unroll
     for (int k = 0; k < N; ++k) {
-        const int ppos = 63 - (int)(win & 63ull);
+        const int ppos = 63 - (int)(win & 63u);
         const int pl = pivot_lane(alive, pos, ppos);
         const bool isp = alive && pos == ppos;
         const double pr = readlane_f64(ar[k], pl), pi = readlane_f64(ai[k], pl);
@@ -159,7 +150,7 @@ __device__ __attribute__((always_inline)) inline void lu_det_rows_complex(double
                 ar[k + 1] = ar[k + 1] - (lr * br - li * bi);
                 ai[k + 1] = ai[k + 1] - (lr * bi + li * br);
             }
-            win = wave_max_u64(alive ? pivot_key(fma(ar[k + 1], ar[k + 1], ai[k + 1] * ai[k + 1]), pos) : 0ull);
+            win = wave_max_u32(alive ? pivot_key32(fma(ar[k + 1], ar[k + 1], ai[k + 1] * ai[k + 1]), pos) : 0u);
 #pragma unroll
             for (int jj = k + 2; jj < N; ++jj) {
                 const double br = readlane_f64(ar[jj], pl), bi = readlane_f64(ai[jj], pl);

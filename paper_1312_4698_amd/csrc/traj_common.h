@@ -32,11 +32,6 @@ __device__ inline ConstProblem opaque(const ProblemDev *P)
     return (ConstProblem)v;
 }
 
-__device__ inline unsigned long long pivot_key(double mag, int pos)
-{
-    return (dbits(mag) & ~63ull) | (unsigned long long)(63 - pos);
-}
-
 // 32-bit pivot key: the high word of the (non-negative) magnitude's bits with
 // its low six bits replaced by 63 - pos.  Keys order as the magnitudes
 // truncated to 14 mantissa bits, ties going to the lowest position (partial
