@@ -78,11 +78,17 @@ __device__ inline unsigned group_max_key(unsigned *keys, int lane, unsigned mine
         v[4 * qd + 2] = t.z;
         v[4 * qd + 3] = t.w;
     }
-    unsigned m = v[0];
+    // a tree of three-input maxima (v_max3_u32)
+    unsigned t[(G + 2) / 3];
+    int nt = 0;
+#pragma unroll
+    for (int i = 0; i < G; i += 3)
+        t[nt++] = (i + 2 < G) ? max(max(v[i], v[i + 1]), v[i + 2]) : (i + 1 < G ? max(v[i], v[i + 1]) : v[i]);
+    unsigned m = t[0];
     int i = 1;
 #pragma unroll
-    for (; i + 1 < G; i += 2) m = max(m, max(v[i], v[i + 1]));
-    if (i < G) m = max(m, v[i]);
+    for (; i + 1 < nt; i += 2) m = max(max(m, t[i]), t[i + 1]);
+    if (i < nt) m = max(m, t[i]);
     return m;
 }
 
@@ -129,9 +135,11 @@ __device__ inline double lu_det_real2(double (&a0)[N], double (&a1)[N], int pos0
         alive0 = alive0 && !isp0;
         alive1 = alive1 && !isp1;
         if (k + 1 < N) {
+            // rows already used as pivots are updated too (their keys are
+            // masked, so their values are never read again)
             const double inv = rcp_nr(pk);
-            const double l0 = alive0 ? a0[k] * inv : 0.0;
-            const double l1 = alive1 ? a1[k] * inv : 0.0;
+            const double l0 = a0[k] * inv;
+            const double l1 = a1[k] * inv;
             const double v = piv[k + 1];
             a0[k + 1] = fma(-l0, v, a0[k + 1]);
             a1[k + 1] = fma(-l1, v, a1[k + 1]);
@@ -182,8 +190,8 @@ __device__ inline void lu_det_complex(double (&ar)[N], double (&ai)[N], int pos,
         alive = alive && !isp;
         if (k + 1 < N) {
             const double inv = rcp_nr(fma(pr, pr, pi * pi));
-            const double lr = alive ? (ar[k] * pr + ai[k] * pi) * inv : 0.0;
-            const double li = alive ? (ai[k] * pr - ar[k] * pi) * inv : 0.0;
+            const double lr = (ar[k] * pr + ai[k] * pi) * inv;  // a used pivot row is updated too, never read again
+            const double li = (ai[k] * pr - ar[k] * pi) * inv;
             {
                 const double br = piv[2 * (k + 1)], bi = piv[2 * (k + 1) + 1];
                 ar[k + 1] = ar[k + 1] - (lr * br - li * bi);
