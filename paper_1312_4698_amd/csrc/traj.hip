@@ -43,18 +43,30 @@ namespace scivr {
 namespace {
 
 template <int F>
-struct alignas(16) GroupLds {
+struct GroupCore {
     static constexpr int N2 = 2 * F;
     static constexpr int KS = (F + 3) & ~3;
-    // bytes of the fields below; the padding makes the stride between groups
-    // 16 B more than a multiple of the 256-byte bank row, so the groups'
-    // simultaneous broadcast reads fall into different banks
-    static constexpr int BYTES = 8 * 2 * N2 + 4 * KS;
-    static constexpr int PAD = ((16 - BYTES % 256) % 256 + 256) % 256 / 8;
+    static constexpr int RB = F < 8 ? F : 8;  // time samples per amplitude ring
     double pivM[N2];                   // pivot row of the real elimination
     double pivA[N2];                   // pivot row of the complex elimination (re, im interleaved)
     unsigned keys[KS];                 // one pivot key per lane of the group
-    double pad[PAD > 0 ? PAD : 2];
+    // amplitude ring: per time sample, the exponent and the phase (overlap +
+    // action) of the amplitude, the det(A) ratio z whose argument advances
+    // the prefactor branch, the status flag, and the branch increment
+    double rex[RB], rph[RB], rzr[RB], rzi[RB], rinc[RB];
+    double rtheta, rphi;               // branch and prefactor phase after the last finished sample
+    int rflag[RB];
+    int rgood;
+};
+
+// A group's LDS block, padded so that the stride between groups is 16 B more
+// than a multiple of the 256-byte bank row: the groups' simultaneous
+// broadcast reads then fall into different banks.
+template <int F>
+struct alignas(16) GroupLds : GroupCore<F> {
+    static constexpr int BYTES = (int)((sizeof(GroupCore<F>) + 15) & ~(size_t)15);
+    static constexpr int PADB = ((16 - BYTES % 256) % 256 + 256) % 256;
+    char pad[(BYTES - (int)sizeof(GroupCore<F>)) + (PADB > 0 ? PADB : 256)];
 };
 
 // Pivot search of one elimination step: lane `lane` of the group of G lanes
@@ -324,21 +336,19 @@ traj_kernel(TrajArgs A, const ProblemDev *__restrict__ P0)
         }
         return ex;
     };
-    // store the amplitude <chi|p,q> e^{i(S + phi)} of time sample t (zero when bad)
-    auto store_amplitude = [&](auto PP, int t) {
-        double ph;
-        const double ex = overlap(PP, ph);
+    // store the amplitude e^{ex} e^{i phase} of time sample t (zero when bad)
+    auto put_amplitude = [&](auto PP, int t, double ex, double phase, bool g) {
         double s, co;
-        dsincos(ph + S.value() + phi, &PP->mc, &s, &co);
+        dsincos(phase, &PP->mc, &s, &co);
         if constexpr (!MIXED) {
             const double mag = dexp(ex, &PP->mc);
             double2 r;
-            r.x = good ? mag * co : 0.0;
-            r.y = good ? mag * s : 0.0;
+            r.x = g ? mag * co : 0.0;
+            r.y = g ? mag * s : 0.0;
             A.amp[(int64_t)t * NP + jr] = r;
         } else {
             const double mag = ldexp(dexp(ex, &PP->mc), escale);
-            const float re = good ? (float)(mag * co) : 0.f, im = good ? (float)(mag * s) : 0.f;
+            const float re = g ? (float)(mag * co) : 0.f, im = g ? (float)(mag * s) : 0.f;
             _Float16 h[4];
             split_f16(re, h[0], h[1]);
             split_f16(im, h[2], h[3]);
@@ -347,15 +357,21 @@ traj_kernel(TrajArgs A, const ProblemDev *__restrict__ P0)
             for (int pl = 0; pl < 4; ++pl) A.amp16[pl * A.plane + e] = h[pl];
         }
     };
+    // the amplitude <chi|p,q> e^{i(S + phi)} of the published state
+    auto store_amplitude = [&](auto PP, int t) {
+        double ph;
+        const double ex = overlap(PP, ph);
+        put_amplitude(PP, t, ex, ph + S.value() + phi, good);
+    };
 
-    if (A.step_begin == 0 && c == 0) {
-        if constexpr (MIXED) {
+    if (A.step_begin == 0) {
+        if constexpr (MIXED) {  // every lane: the ring's lanes store with it
             double ph;
             const double ex0 = overlap(P, ph);
             // 2^escale ~ 1/|<chi|z_0>|, exact power of two, bounded so |amp| 2^escale < 2^12
             escale = (int)fmin(fmax(floor(-ex0 * 1.4426950408889634), 0.0), 12.0);
         }
-        if (live) store_amplitude(P, 0);
+        if (c == 0 && live) store_amplitude(P, 0);
     }
 
     for (int step = A.step_begin; step < A.step_end; ++step) {
@@ -439,7 +455,6 @@ traj_kernel(TrajArgs A, const ProblemDev *__restrict__ P0)
         }
 
         const int stp = step + 1;
-        const double t = (double)stp * Ps->dt;
 
         // det(A) = det(A^T) and det(M) = det(M^T): the rows of the transposes are
         // columns, and lane c already holds columns c (d/dp0_c) and F + c
@@ -496,6 +511,12 @@ traj_kernel(TrajArgs A, const ProblemDev *__restrict__ P0)
         // det(A_t) conj(det(A_{t-dt})) e^{i dt sum gamma}, which equals the step of
         // arg(det(A) e^{i t sum gamma}) wrapped to (-pi, pi]; det(A) is rescaled by
         // a power of two (argument unchanged) so the products cannot overflow.
+        // Lane 0 puts the step's inputs of the amplitude into the group's ring;
+        // every RB steps (and at the last step of the launch) RB lanes finish
+        // one time sample each: the argument, the branch as the running sum of
+        // the arguments in time order, phi, the status, exp and sincos.
+        constexpr int RB = GroupCore<F>::RB;
+        const int slot = stp % RB;
         if (c == 0) {
             int ex;
             (void)frexp(fmax(fabs(dAr), fabs(dAi)), &ex);
@@ -503,14 +524,44 @@ traj_kernel(TrajArgs A, const ProblemDev *__restrict__ P0)
             dAi = ldexp(dAi, -ex);
             const double ur = dAr * prev_r + dAi * prev_i;
             const double ui = dAi * prev_r - dAr * prev_i;
-            const double zr = ur * Ps->cos_gdt - ui * Ps->sin_gdt;
-            const double zi = ur * Ps->sin_gdt + ui * Ps->cos_gdt;
-            theta += datan2(zi, zr, &Ps->mc);
+            L.rzr[slot] = ur * Ps->cos_gdt - ui * Ps->sin_gdt;
+            L.rzi[slot] = ur * Ps->sin_gdt + ui * Ps->cos_gdt;
             prev_r = dAr;
             prev_i = dAi;
-            phi = 0.5 * (theta - Ps->sum_gamma * t);
-            if (!isfinite(phi) || !isfinite(S.value())) good = false;
-            if (live) store_amplitude(Ps, stp);
+            double ph;
+            L.rex[slot] = overlap(Ps, ph);
+            L.rph[slot] = ph + S.value();
+            L.rflag[slot] = (good && isfinite(S.value())) ? 1 : 0;
+        }
+        if (slot == RB - 1 || stp == A.step_end) {
+            const int first = max(stp - slot, A.step_begin + 1);  // first time sample in the ring
+            const int cnt = stp - first + 1;
+            const int sl = (first + c) % RB;                       // this lane's sample, if c < cnt
+            lds_order();
+            if (c < cnt) L.rinc[sl] = datan2(L.rzi[sl], L.rzr[sl], &Ps->mc);
+            lds_order();
+            if (c < cnt) {
+                double th = theta;
+#pragma unroll
+                for (int u = 0; u < RB; ++u)
+                    if (u <= c) th += L.rinc[(first + u) % RB];
+                const int ts = first + c;
+                const double ph_ = 0.5 * (th - Ps->sum_gamma * ((double)ts * Ps->dt));
+                // the flag holds the sticky status at that step; a non-finite
+                // branch stays non-finite for every later sample
+                const bool g = L.rflag[sl] != 0 && isfinite(ph_);
+                if (live) put_amplitude(Ps, ts, L.rex[sl], L.rph[sl] + ph_, g);
+                if (c == cnt - 1) {
+                    L.rtheta = th;
+                    L.rphi = ph_;
+                    L.rgood = g ? 1 : 0;
+                }
+            }
+            lds_order();
+            theta = L.rtheta;
+            phi = L.rphi;
+            good = L.rgood != 0;
+            lds_order();
         }
     }
 
