@@ -42,31 +42,42 @@
 namespace scivr {
 namespace {
 
+// Waves per SIMD the register allocator must allow (unified 512-register file).
+template <int F>
+constexpr int traj_waves() { return F <= 3 ? 4 : (F <= 6 ? 3 : (F <= 12 ? 2 : 1)); }
+
 template <int F>
 struct GroupCore {
     static constexpr int N2 = 2 * F;
     static constexpr int KS = (F + 3) & ~3;
     static constexpr int RB = F < 8 ? F : 8;  // time samples per amplitude ring
+    // the overlap's mode terms go through the ring (one per lane) where the
+    // kernel runs at most two waves per SIMD; with more waves the LDS it takes
+    // would cost occupancy, and lane 0 sums them itself
+    static constexpr bool OVL = traj_waves<F>() <= 2;
+    static constexpr int OT = OVL ? F : 1;
     double pivM[N2];                   // pivot row of the real elimination
     double pivA[N2];                   // pivot row of the complex elimination (re, im interleaved)
     unsigned keys[KS];                 // one pivot key per lane of the group
-    // amplitude ring: per time sample, the exponent and the phase (overlap +
-    // action) of the amplitude, the det(A) ratio z whose argument advances
-    // the prefactor branch, the status flag, and the branch increment
-    double rex[RB], rph[RB], rzr[RB], rzi[RB], rinc[RB];
+    // amplitude ring: per time sample, each mode's terms of the exponent and
+    // the phase of <chi|p,q>, the action, the det(A) ratio z whose argument
+    // advances the prefactor branch, the status flag, and the branch increment
+    double rex[RB][OT], rph[RB][OT];  // without OVL: lane 0's sums, the phase with the action added
+    double rS[OVL ? RB : 1], rzr[RB], rzi[RB], rinc[RB];
     double rtheta, rphi;               // branch and prefactor phase after the last finished sample
     int rflag[RB];
     int rgood;
 };
 
-// A group's LDS block, padded so that the stride between groups is 16 B more
-// than a multiple of the 256-byte bank row: the groups' simultaneous
-// broadcast reads then fall into different banks.
+// A group's LDS block, padded to an odd multiple of 16 B: the groups of a
+// wave then start 4 * odd banks apart modulo the 64 four-byte banks, so up to
+// 16 groups' simultaneous 16-byte broadcast reads fall into different banks.
 template <int F>
 struct alignas(16) GroupLds : GroupCore<F> {
     static constexpr int BYTES = (int)((sizeof(GroupCore<F>) + 15) & ~(size_t)15);
-    static constexpr int PADB = ((16 - BYTES % 256) % 256 + 256) % 256;
-    char pad[(BYTES - (int)sizeof(GroupCore<F>)) + (PADB > 0 ? PADB : 256)];
+    static constexpr int PADB = ((BYTES / 16) % 2 == 0) ? 16 : 0;
+    static constexpr int PADN = (BYTES - (int)sizeof(GroupCore<F>)) + PADB;
+    char pad[PADN > 0 ? PADN : 32];  // 32 keeps the parity where no padding is needed
 };
 
 // Pivot search of one elimination step: lane `lane` of the group of G lanes
@@ -224,10 +235,6 @@ __device__ inline void lu_det_complex(double (&ar)[N], double (&ai)[N], int pos,
     di = zi;
 }
 
-// Waves per SIMD the register allocator must allow (unified 512-register file).
-template <int F>
-constexpr int traj_waves() { return F <= 3 ? 4 : (F <= 6 ? 3 : (F <= 12 ? 2 : 1)); }
-
 // The trajectory kernel.  MIXED = false: every trajectory quantity in FP64.
 // MIXED = true: the trajectory (p, q), the potential, gradient and Hessian
 // diagonal and the action (Kahan-compensated) in FP32; the tangent columns,
@@ -244,8 +251,9 @@ traj_kernel(TrajArgs A, const ProblemDev *__restrict__ P0)
     constexpr int TPW = 64 / F;
     __shared__ GroupLds<F> lds_all[TPW];
     __shared__ double lam_lds[F * F];  // coupling matrix, shared by the wave's groups
+    static_assert((sizeof(GroupLds<F>) / 16) % 2 == 1, "group stride must be an odd multiple of 16 B");
     __shared__ R qv_all[TPW][F + (F & 1)], pm_all[TPW][F + (F & 1)];
-    __shared__ R pg_all[TPW][F + (F & 1)], ph_all[TPW][F + (F & 1)], pv_all[TPW][F + (F & 1)];
+    __shared__ R ph_all[TPW][F + (F & 1)], pv_all[TPW][F + (F & 1)];
     // The p halves of the lane's two monodromy columns wait in LDS while the
     // eliminations run where the register file cannot hold them, the rows of
     // M^T and the pivot traffic at once (F <= 6, three or four waves per SIMD;
@@ -263,8 +271,7 @@ traj_kernel(TrajArgs A, const ProblemDev *__restrict__ P0)
     if (grp >= TPW) return;
     const int c = lane - grp * F;  // degree of freedom owned by this lane
     GroupLds<F> &L = lds_all[grp];
-    R *qv = qv_all[grp], *pm = pm_all[grp], *pg = pg_all[grp], *phd = ph_all[grp], *pv = pv_all[grp];
-    (void)pg;
+    R *qv = qv_all[grp], *pm = pm_all[grp], *phd = ph_all[grp], *pv = pv_all[grp];
     const int64_t j = (int64_t)blockIdx.x * TPW + grp;
     const bool live = j < A.n;
     const int64_t jr = live ? j : 0;
@@ -511,7 +518,8 @@ traj_kernel(TrajArgs A, const ProblemDev *__restrict__ P0)
         // det(A_t) conj(det(A_{t-dt})) e^{i dt sum gamma}, which equals the step of
         // arg(det(A) e^{i t sum gamma}) wrapped to (-pi, pi]; det(A) is rescaled by
         // a power of two (argument unchanged) so the products cannot overflow.
-        // Lane 0 puts the step's inputs of the amplitude into the group's ring;
+        // Lane 0 puts the step's inputs of the amplitude into the group's ring
+        // (each lane adds its mode's terms of the overlap);
         // every RB steps (and at the last step of the launch) RB lanes finish
         // one time sample each: the argument, the branch as the running sum of
         // the arguments in time order, phi, the status, exp and sincos.
@@ -528,10 +536,20 @@ traj_kernel(TrajArgs A, const ProblemDev *__restrict__ P0)
             L.rzi[slot] = ur * Ps->sin_gdt + ui * Ps->cos_gdt;
             prev_r = dAr;
             prev_i = dAi;
-            double ph;
-            L.rex[slot] = overlap(Ps, ph);
-            L.rph[slot] = ph + S.value();
             L.rflag[slot] = (good && isfinite(S.value())) ? 1 : 0;
+            if constexpr (GroupCore<F>::OVL) {
+                L.rS[slot] = S.value();
+            } else {
+                double ph;
+                L.rex[slot][0] = overlap(Ps, ph);
+                L.rph[slot][0] = ph + S.value();
+            }
+        }
+        if constexpr (GroupCore<F>::OVL) {  // mode c's terms of <chi|p,q>
+            const double dqe = Ps->q_eq[c] - (double)qc;
+            const double dpe = Ps->p_eq[c] - (double)pc;
+            L.rex[slot][c] = -0.25 * Ps->gamma[c] * dqe * dqe - dpe * dpe * Ps->inv4gamma[c];
+            L.rph[slot][c] = 0.5 * dqe * (Ps->p_eq[c] + (double)pc);
         }
         if (slot == RB - 1 || stp == A.step_end) {
             const int first = max(stp - slot, A.step_begin + 1);  // first time sample in the ring
@@ -550,7 +568,14 @@ traj_kernel(TrajArgs A, const ProblemDev *__restrict__ P0)
                 // the flag holds the sticky status at that step; a non-finite
                 // branch stays non-finite for every later sample
                 const bool g = L.rflag[sl] != 0 && isfinite(ph_);
-                if (live) put_amplitude(Ps, ts, L.rex[sl], L.rph[sl] + ph_, g);
+                double ex = 0.0, ph = 0.0;
+#pragma unroll
+                for (int i = 0; i < GroupCore<F>::OT; ++i) {
+                    ex += L.rex[sl][i];
+                    ph += L.rph[sl][i];
+                }
+                if constexpr (GroupCore<F>::OVL) ph = ph + L.rS[sl];
+                if (live) put_amplitude(Ps, ts, ex, ph + ph_, g);
                 if (c == cnt - 1) {
                     L.rtheta = th;
                     L.rphi = ph_;
