@@ -217,16 +217,16 @@ __device__ inline void lu_det_complex(double (&ar)[N], double (&ai)[N], int pos,
             const double li = (ai[k] * pr - ar[k] * pi) * inv;
             {
                 const double br = piv[2 * (k + 1)], bi = piv[2 * (k + 1) + 1];
-                ar[k + 1] = ar[k + 1] - (lr * br - li * bi);
-                ai[k + 1] = ai[k + 1] - (lr * bi + li * br);
+                ar[k + 1] = fma(-lr, br, fma(li, bi, ar[k + 1]));
+                ai[k + 1] = fma(-lr, bi, fma(-li, br, ai[k + 1]));
             }
             const double m2 = fma(ar[k + 1], ar[k + 1], ai[k + 1] * ai[k + 1]);
             win = group_max_key<N>(keys, lane, alive ? pivot_key32(m2, pos) : 0u);
 #pragma unroll
             for (int jj = k + 2; jj < N; ++jj) {
                 const double br = piv[2 * jj], bi = piv[2 * jj + 1];
-                ar[jj] = ar[jj] - (lr * br - li * bi);
-                ai[jj] = ai[jj] - (lr * bi + li * br);
+                ar[jj] = fma(-lr, br, fma(li, bi, ar[jj]));
+                ai[jj] = fma(-lr, bi, fma(-li, br, ai[jj]));
             }
         }
     }

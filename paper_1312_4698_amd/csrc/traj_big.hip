@@ -109,7 +109,9 @@ __device__ __attribute__((always_inline)) inline double lu_det_rows(double (&a)[
         pos = (alive && pos == k) ? ppos : pos;
         alive = alive && !isp;
         if (k + 1 < N) {
-            const double l = alive ? a[k] * rcp_nr(pk) : 0.0;
+            // rows out of play (used pivots, lanes beyond N) are updated too:
+            // their keys are masked, so their values are never read again
+            const double l = a[k] * rcp_nr(pk);
             a[k + 1] = fma(-l, readlane_f64(a[k + 1], pl), a[k + 1]);
             win = wave_max_u32(alive ? pivot_key32(fabs(a[k + 1]), pos) : 0u);
 #pragma unroll
@@ -143,19 +145,19 @@ __device__ __attribute__((always_inline)) inline void lu_det_rows_complex(double
         alive = alive && !isp;
         if (k + 1 < N) {
             const double inv = rcp_nr(fma(pr, pr, pi * pi));
-            const double lr = alive ? (ar[k] * pr + ai[k] * pi) * inv : 0.0;
-            const double li = alive ? (ai[k] * pr - ar[k] * pi) * inv : 0.0;
+            const double lr = (ar[k] * pr + ai[k] * pi) * inv;  // rows out of play: as in lu_det_rows
+            const double li = (ai[k] * pr - ar[k] * pi) * inv;
             {
                 const double br = readlane_f64(ar[k + 1], pl), bi = readlane_f64(ai[k + 1], pl);
-                ar[k + 1] = ar[k + 1] - (lr * br - li * bi);
-                ai[k + 1] = ai[k + 1] - (lr * bi + li * br);
+                ar[k + 1] = fma(-lr, br, fma(li, bi, ar[k + 1]));
+                ai[k + 1] = fma(-lr, bi, fma(-li, br, ai[k + 1]));
             }
             win = wave_max_u32(alive ? pivot_key32(fma(ar[k + 1], ar[k + 1], ai[k + 1] * ai[k + 1]), pos) : 0u);
 #pragma unroll
             for (int jj = k + 2; jj < N; ++jj) {
                 const double br = readlane_f64(ar[jj], pl), bi = readlane_f64(ai[jj], pl);
-                ar[jj] = ar[jj] - (lr * br - li * bi);
-                ai[jj] = ai[jj] - (lr * bi + li * br);
+                ar[jj] = fma(-lr, br, fma(li, bi, ar[jj]));
+                ai[jj] = fma(-lr, bi, fma(-li, br, ai[jj]));
             }
         }
     }
