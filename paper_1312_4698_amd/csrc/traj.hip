@@ -80,6 +80,16 @@ struct alignas(16) GroupLds : GroupCore<F> {
     char pad[PADN > 0 ? PADN : 32];  // 32 keeps the parity where no padding is needed
 };
 
+// Publishes one element of a pivot row.  The stores stay single 8-byte
+// stores: merged into 16-byte stores they need their two doubles in four
+// consecutive registers, and the register copies that packs them cost more
+// than the extra LDS instructions.
+__device__ inline void publish(double *row, int j, double v)
+{
+    typedef __attribute__((address_space(3))) volatile double lds_vf64;
+    ((lds_vf64 *)row)[j] = v;
+}
+
 // Pivot search of one elimination step: lane `lane` of the group of G lanes
 // publishes its best key, and every lane reads the G keys back (16-byte
 // broadcast reads) and takes their maximum.  The slots are rewritten at the
@@ -144,11 +154,11 @@ __device__ inline double lu_det_real2(double (&a0)[N], double (&a1)[N], int pos0
         lds_order();
         if (isp0) {
 #pragma unroll
-            for (int jj = k; jj < N; ++jj) piv[jj] = a0[jj];
+            for (int jj = k; jj < N; ++jj) publish(piv, jj, a0[jj]);
         }
         if (isp1) {
 #pragma unroll
-            for (int jj = k; jj < N; ++jj) piv[jj] = a1[jj];
+            for (int jj = k; jj < N; ++jj) publish(piv, jj, a1[jj]);
         }
         lds_order();
         const double pk = piv[k];
@@ -199,8 +209,8 @@ __device__ inline void lu_det_complex(double (&ar)[N], double (&ai)[N], int pos,
         if (isp) {
 #pragma unroll
             for (int jj = k; jj < N; ++jj) {
-                piv[2 * jj] = ar[jj];
-                piv[2 * jj + 1] = ai[jj];
+                publish(piv, 2 * jj, ar[jj]);
+                publish(piv, 2 * jj + 1, ai[jj]);
             }
         }
         lds_order();
