@@ -51,9 +51,9 @@ struct GroupCore {
     static constexpr int N2 = 2 * F;
     static constexpr int KS = (F + 3) & ~3;
     static constexpr int RB = F < 8 ? F : 8;  // time samples per amplitude ring
-    // the overlap's mode terms go through the ring (one per lane) where the
-    // kernel runs at most two waves per SIMD; with more waves the LDS it takes
-    // would cost occupancy, and lane 0 sums them itself
+    // the overlap's mode terms and the action's parts go through the ring (one
+    // per lane) where the kernel runs at most two waves per SIMD; with more
+    // waves the LDS it takes would cost occupancy, and lane 0 sums them itself
     static constexpr bool OVL = traj_waves<F>() <= 2;
     static constexpr int OT = OVL ? F : 1;
     double pivM[N2];                   // pivot row of the real elimination
@@ -63,7 +63,8 @@ struct GroupCore {
     // the phase of <chi|p,q>, the action, the det(A) ratio z whose argument
     // advances the prefactor branch, the status flag, and the branch increment
     double rex[RB][OT], rph[RB][OT];  // without OVL: lane 0's sums, the phase with the action added
-    double rS[OVL ? RB : 1], rzr[RB], rzi[RB], rinc[RB];
+    double rS[RB][OT];                 // with OVL: each lane's part of the action
+    double rzr[RB], rzi[RB], rinc[RB];
     double rtheta, rphi;               // branch and prefactor phase after the last finished sample
     int rflag[RB];
     int rgood;
@@ -269,6 +270,7 @@ traj_kernel(TrajArgs A, const ProblemDev *__restrict__ P0)
     // M^T and the pivot traffic at once (F <= 6, three or four waves per SIMD;
     // at two waves per SIMD the LDS round trip costs more than it saves).
     constexpr bool STASH = F <= 6;
+    constexpr bool OVL = GroupCore<F>::OVL;
     __shared__ double stash_all[STASH ? TPW : 1][2][F][F];
 
     const int lane = threadIdx.x;
@@ -325,7 +327,7 @@ traj_kernel(TrajArgs A, const ProblemDev *__restrict__ P0)
         }
         pc = (R)A.p[c * NP + jr];
         qc = (R)A.q[c * NP + jr];
-        S.load(A.scal[SC_S * NP + jr], A.scal[SC_SCOMP * NP + jr]);
+        if (c == 0) S.load(A.scal[SC_S * NP + jr], A.scal[SC_SCOMP * NP + jr]);
         theta = A.scal[SC_THETA * NP + jr];
         prev_r = A.scal[SC_PREV_RE * NP + jr];
         prev_i = A.scal[SC_PREV_IM * NP + jr];
@@ -398,7 +400,9 @@ traj_kernel(TrajArgs A, const ProblemDev *__restrict__ P0)
             ConstProblem Pk = opaque(P0);
             // ---- drift ----
             const double h = Pk->hd[s];
-            if (c == 0) {  // the action is carried by lane 0 only
+            if constexpr (OVL) {  // each lane carries its mode's part of the action
+                S.add(h * (double)((R)0.5 * pc * pc));
+            } else if (c == 0) {  // lane 0 carries the whole action
                 R kin = 0;
 #pragma unroll
                 for (int i = 0; i < F; ++i) {
@@ -436,10 +440,12 @@ traj_kernel(TrajArgs A, const ProblemDev *__restrict__ P0)
             const R vc = (R)0.5 * kc * qc * qc + Dc * one_e * one_e + (R)0.5 * qc * qc * sm;
             pc = fma(-(R)hk, gc, pc);
             phd[c] = hc;
-            pv[c] = vc;
+            if constexpr (!OVL) pv[c] = vc;
             pm[c] = pc;
             lds_order();
-            if (c == 0) {
+            if constexpr (OVL) {
+                S.add(-hk * (double)vc);
+            } else if (c == 0) {
                 R V = 0;
 #pragma unroll
                 for (int i = 0; i < F; ++i) V += pv[i];
@@ -546,20 +552,21 @@ traj_kernel(TrajArgs A, const ProblemDev *__restrict__ P0)
             L.rzi[slot] = ur * Ps->sin_gdt + ui * Ps->cos_gdt;
             prev_r = dAr;
             prev_i = dAi;
-            L.rflag[slot] = (good && isfinite(S.value())) ? 1 : 0;
-            if constexpr (GroupCore<F>::OVL) {
-                L.rS[slot] = S.value();
+            if constexpr (OVL) {
+                L.rflag[slot] = good ? 1 : 0;  // the finite-action test is on the sum
             } else {
+                L.rflag[slot] = (good && isfinite(S.value())) ? 1 : 0;
                 double ph;
                 L.rex[slot][0] = overlap(Ps, ph);
                 L.rph[slot][0] = ph + S.value();
             }
         }
-        if constexpr (GroupCore<F>::OVL) {  // mode c's terms of <chi|p,q>
+        if constexpr (OVL) {  // mode c's terms of <chi|p,q> and part of the action
             const double dqe = Ps->q_eq[c] - (double)qc;
             const double dpe = Ps->p_eq[c] - (double)pc;
             L.rex[slot][c] = -0.25 * Ps->gamma[c] * dqe * dqe - dpe * dpe * Ps->inv4gamma[c];
             L.rph[slot][c] = 0.5 * dqe * (Ps->p_eq[c] + (double)pc);
+            L.rS[slot][c] = S.value();
         }
         if (slot == RB - 1 || stp == A.step_end) {
             const int first = max(stp - slot, A.step_begin + 1);  // first time sample in the ring
@@ -577,14 +584,20 @@ traj_kernel(TrajArgs A, const ProblemDev *__restrict__ P0)
                 const double ph_ = 0.5 * (th - Ps->sum_gamma * ((double)ts * Ps->dt));
                 // the flag holds the sticky status at that step; a non-finite
                 // branch stays non-finite for every later sample
-                const bool g = L.rflag[sl] != 0 && isfinite(ph_);
+                bool g = L.rflag[sl] != 0 && isfinite(ph_);
                 double ex = 0.0, ph = 0.0;
 #pragma unroll
                 for (int i = 0; i < GroupCore<F>::OT; ++i) {
                     ex += L.rex[sl][i];
                     ph += L.rph[sl][i];
                 }
-                if constexpr (GroupCore<F>::OVL) ph = ph + L.rS[sl];
+                if constexpr (OVL) {
+                    double St = 0.0;
+#pragma unroll
+                    for (int i = 0; i < F; ++i) St += L.rS[sl][i];
+                    g = g && isfinite(St);  // the parts are running sums: once non-finite, always
+                    ph = ph + St;
+                }
                 if (live) put_amplitude(Ps, ts, ex, ph + ph_, g);
                 if (c == cnt - 1) {
                     L.rtheta = th;
@@ -598,6 +611,19 @@ traj_kernel(TrajArgs A, const ProblemDev *__restrict__ P0)
             good = L.rgood != 0;
             lds_order();
         }
+    }
+
+    if constexpr (OVL) {  // the whole action into lane 0
+        lds_order();
+        L.rS[0][c] = S.value();
+        lds_order();
+        if (c == 0) {
+            double St = 0.0;
+#pragma unroll
+            for (int i = 0; i < F; ++i) St += L.rS[0][i];
+            S.set_total(St);
+        }
+        lds_order();
     }
 
     // ---- save the state for a later continuation and for inspection ----

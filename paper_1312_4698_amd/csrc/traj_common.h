@@ -63,6 +63,7 @@ struct Action<false> {
     __device__ void add(double x) { s += x; }
     __device__ double value() const { return s; }
     __device__ void load(double v, double) { s = v; }
+    __device__ void set_total(double v) { s = v; }
     __device__ double hi() const { return s; }
     __device__ double lo() const { return 0.0; }
 };
@@ -75,6 +76,12 @@ struct Action<true> {
     {
         k.s = (float)v;
         k.c = (float)comp;
+    }
+    // the compensated pair (s, c) with s - c ~ v
+    __device__ void set_total(double v)
+    {
+        k.s = (float)v;
+        k.c = (float)((double)k.s - v);
     }
     __device__ double hi() const { return (double)k.s; }
     __device__ double lo() const { return (double)k.c; }
