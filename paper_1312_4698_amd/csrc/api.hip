@@ -55,7 +55,7 @@ void free_all(scivr_ctx *c)
     void *ptrs[] = {c->d_prob,   c->d_p0,        c->d_q0,           c->d_logrho,  c->d_p,     c->d_q,
                     c->d_scal,   c->d_M,         c->d_amp,          c->d_amp16,   c->d_phase, c->d_weight,
                     c->d_part_spec, c->d_part_contrib, c->d_contrib, c->d_total, c->d_ngood, c->d_goodw,
-                    c->d_goodw_row};
+                    c->d_goodw_row, c->d_spart};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     for (auto &e : c->events) {
@@ -214,6 +214,7 @@ scivr_status scivr_create(const scivr_problem *p, int32_t device, scivr_ctx **ou
     A(dalloc(&c->d_logrho, NP));
     A(dalloc(&c->d_p, F * NP));
     A(dalloc(&c->d_q, F * NP));
+    A(dalloc(&c->d_spart, F * NP));
     A(dalloc(&c->d_scal, NSCAL * NP));
     A(dalloc(&c->d_M, G2 * NP));
     const bool mixed = c->precision == SCIVR_PRECISION_MIXED;
@@ -325,6 +326,7 @@ scivr_status scivr_propagate(scivr_ctx *ctx, int32_t step_begin, int32_t step_en
     a.p = ctx->d_p;
     a.q = ctx->d_q;
     a.scal = ctx->d_scal;
+    a.spart = ctx->d_spart;
     a.Mst = ctx->d_M;
     a.amp = ctx->d_amp;
     a.amp16 = ctx->d_amp16;

@@ -27,6 +27,7 @@ struct scivr_ctx {
     scivr::ProblemDev *d_prob = nullptr;
     double *d_p0 = nullptr, *d_q0 = nullptr, *d_logrho = nullptr;
     double *d_p = nullptr, *d_q = nullptr, *d_scal = nullptr, *d_M = nullptr;
+    double *d_spart = nullptr;      // per-mode parts of the action between launches [F][npad]
     double2 *d_amp = nullptr, *d_phase = nullptr;  // FP64 form
     _Float16 *d_amp16 = nullptr;                    // mixed form: 4 planes [nt16 / 8][npad][8]
     int32_t nt16 = 0;                               // time samples per plane (multiple of 32)

@@ -41,6 +41,8 @@ struct TrajArgs {
     const double *p0, *q0;  // [F][npad]
     double *p, *q;          // [F][npad] state
     double *scal;           // [NSCAL][npad]
+    double *spart;          // [F][npad] per-mode parts of the action, kept between launches
+                            // where the small-F kernel splits the action over its lanes
     double *Mst;            // [(2F)^2][npad], element r*2F + c
     double2 *amp;           // FP64 form: [nt_alloc][npad]
     _Float16 *amp16;        // mixed form: 4 planes [nt_alloc / 8][npad][8]

@@ -327,7 +327,10 @@ traj_kernel(TrajArgs A, const ProblemDev *__restrict__ P0)
         }
         pc = (R)A.p[c * NP + jr];
         qc = (R)A.q[c * NP + jr];
-        if (c == 0) S.load(A.scal[SC_S * NP + jr], A.scal[SC_SCOMP * NP + jr]);
+        if constexpr (OVL)
+            S.unpack(A.spart[c * NP + jr]);  // this lane's part, bit for bit
+        else if (c == 0)
+            S.load(A.scal[SC_S * NP + jr], A.scal[SC_SCOMP * NP + jr]);
         theta = A.scal[SC_THETA * NP + jr];
         prev_r = A.scal[SC_PREV_RE * NP + jr];
         prev_i = A.scal[SC_PREV_IM * NP + jr];
@@ -613,7 +616,8 @@ traj_kernel(TrajArgs A, const ProblemDev *__restrict__ P0)
         }
     }
 
-    if constexpr (OVL) {  // the whole action into lane 0
+    if constexpr (OVL) {  // each lane's part for a continuation, the whole action into lane 0
+        if (live) A.spart[c * NP + jr] = S.pack();
         lds_order();
         L.rS[0][c] = S.value();
         lds_order();

@@ -64,6 +64,8 @@ struct Action<false> {
     __device__ double value() const { return s; }
     __device__ void load(double v, double) { s = v; }
     __device__ void set_total(double v) { s = v; }
+    __device__ double pack() const { return s; }
+    __device__ void unpack(double v) { s = v; }
     __device__ double hi() const { return s; }
     __device__ double lo() const { return 0.0; }
 };
@@ -82,6 +84,13 @@ struct Action<true> {
     {
         k.s = (float)v;
         k.c = (float)((double)k.s - v);
+    }
+    // the pair (s, c) bit for bit in one 64-bit word
+    __device__ double pack() const { return __hiloint2double(__float_as_int(k.c), __float_as_int(k.s)); }
+    __device__ void unpack(double v)
+    {
+        k.s = __int_as_float(__double2loint(v));
+        k.c = __int_as_float(__double2hiint(v));
     }
     __device__ double hi() const { return (double)k.s; }
     __device__ double lo() const { return (double)k.c; }

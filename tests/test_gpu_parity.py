@@ -94,10 +94,17 @@ def test_parity_with_oracle(scivr, oracle_mod, F, n, ns, K, emax, sp):
     ctx.close()
 
 
-@pytest.mark.parametrize("F,n", [(3, 200), (30, 40)])
-def test_chunked_propagation_is_identical(scivr, F, n):
-    _say(f"[chunked] F={F}")
-    prob = inputs.morse_quartic(F, F, n_steps=300, n_energies=128)
+@pytest.mark.parametrize("F,n,precision", [
+    (3, 200, inputs.PRECISION_FP64),
+    # F = 9: the action is split over the lanes and the amplitudes go through an
+    # eight-sample ring; the chunk ends 1, 77, 150 leave the ring part-filled
+    (9, 140, inputs.PRECISION_FP64),
+    (9, 140, inputs.PRECISION_MIXED),
+    (30, 40, inputs.PRECISION_FP64),
+])
+def test_chunked_propagation_is_identical(scivr, F, n, precision):
+    _say(f"[chunked] F={F} precision={precision}")
+    prob = inputs.morse_quartic(F, F, n_steps=300, n_energies=128, precision=precision)
     a = _gpu_run(scivr, prob, 5, n)
     b = _gpu_run(scivr, prob, 5, n, chunks=[1, 77, 150])
     for k in ("p", "q", "S", "phi", "M", "good", "detM", "maxdev"):
