@@ -82,17 +82,24 @@ __global__ void __launch_bounds__(256, 1) fourier_f16_kernel(GemmF16Args G)
     const _Float16 *ap = G.amp16 + ((int64_t)kq * G.npad + row0 + ii) * 8;
     const int64_t astep = (int64_t)(GEMM16_BK / 8) * G.npad * 8;
 
-    for (int t0 = 0; t0 < G.nt_pad; t0 += GEMM16_BK) {
-        h8 arh[4], arl[4], aih[4], ail[4];
+    // amplitude fragments of one k-step; the next k-step's are in flight while
+    // the current one is multiplied (the last prefetch re-reads the last k-step)
+    h8 arh[4], arl[4], aih[4], ail[4];
+    auto load = [&](const _Float16 *base, h8(&rh)[4], h8(&rl)[4], h8(&ih)[4], h8(&il)[4]) {
 #pragma unroll
         for (int bi = 0; bi < 4; ++bi) {
-            const _Float16 *a = ap + bi * 16 * 8;
-            arh[bi] = *(const h8 *)(a);
-            arl[bi] = *(const h8 *)(a + P);
-            aih[bi] = *(const h8 *)(a + 2 * P);
-            ail[bi] = *(const h8 *)(a + 3 * P);
+            const _Float16 *a = base + bi * 16 * 8;
+            rh[bi] = *(const h8 *)(a);
+            rl[bi] = *(const h8 *)(a + P);
+            ih[bi] = *(const h8 *)(a + 2 * P);
+            il[bi] = *(const h8 *)(a + 3 * P);
         }
-        ap += astep;
+    };
+    load(ap, arh, arl, aih, ail);
+    for (int t0 = 0; t0 < G.nt_pad; t0 += GEMM16_BK) {
+        if (t0 + GEMM16_BK < G.nt_pad) ap += astep;
+        h8 nrh[4], nrl[4], nih_[4], nil_[4];
+        load(ap, nrh, nrl, nih_, nil_);
 #pragma unroll
         for (int bj = 0; bj < 4; ++bj) {
             // exp(i E t dt) for t = t0 + 8 kq + s, s = 0..7, split into FP16 pairs
@@ -135,6 +142,13 @@ __global__ void __launch_bounds__(256, 1) fourier_f16_kernel(GemmF16Args G)
                 cr[bi][bj] = r;
                 ci[bi][bj] = m;
             }
+        }
+#pragma unroll
+        for (int bi = 0; bi < 4; ++bi) {
+            arh[bi] = nrh[bi];
+            arl[bi] = nrl[bi];
+            aih[bi] = nih_[bi];
+            ail[bi] = nil_[bi];
         }
     }
 
