@@ -156,6 +156,22 @@ scivr_status scivr_propagate(scivr_ctx *ctx, int32_t step_begin, int32_t step_en
 scivr_status scivr_accumulate_spectrum(scivr_ctx *ctx, void *stream);
 
 /*
+ * The same addition to the running totals as scivr_accumulate_spectrum, by
+ * the exact autocorrelation form of the Fourier sums (Eq. (11)): for each
+ * trajectory, |sum_c amp_jc e^{i E c dt}|^2 is a trigonometric polynomial in
+ * E dt whose coefficients are the autocorrelation of amp_j, obtained from a
+ * zero-padded FFT of length L = 2^ceil(log2(2 n_steps)); the weighted
+ * autocorrelation summed over the batch is then evaluated on the energy grid.
+ * The spectrum agrees with scivr_accumulate_spectrum's to rounding.  No
+ * per-trajectory contributions are produced: scivr_read_contributions and
+ * the flow's training on this batch then return SCIVR_ESTATE.  At most 4096
+ * steps (L <= 8192), else SCIVR_EUNSUPPORTED.  The first call allocates about
+ * 17 MB of scratch on the context's device (SCIVR_ENOMEM if that fails).
+ * Other errors as scivr_accumulate_spectrum.
+ */
+scivr_status scivr_accumulate_spectrum_fft(scivr_ctx *ctx, void *stream);
+
+/*
  * Synchronise and write I_k = dt^2/(2 pi T n_good) * total_k to I_host[K]
  * (caller-owned), and the running n_good and n_total.  If n_good is 0 the
  * spectrum is zero-filled and SCIVR_ENOGOOD is returned.  Any output pointer

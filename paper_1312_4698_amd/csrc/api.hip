@@ -55,7 +55,8 @@ void free_all(scivr_ctx *c)
     void *ptrs[] = {c->d_prob,   c->d_p0,        c->d_q0,           c->d_logrho,  c->d_p,     c->d_q,
                     c->d_scal,   c->d_M,         c->d_amp,          c->d_amp16,   c->d_phase, c->d_weight,
                     c->d_part_spec, c->d_part_contrib, c->d_contrib, c->d_total, c->d_ngood, c->d_goodw,
-                    c->d_goodw_row, c->d_spart};
+                    c->d_goodw_row, c->d_spart, c->d_fft_part, c->d_fft_S, c->d_fft_pcorr, c->d_fft_corr,
+                    c->d_fft_C};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     for (auto &e : c->events) {
@@ -404,6 +405,70 @@ scivr_status scivr_accumulate_spectrum(scivr_ctx *ctx, void *stream)
     }
     ctx->n_total += ctx->n_traj;
     ctx->accumulated = true;
+    ctx->contrib_valid = true;
+    return SCIVR_OK;
+}
+
+scivr_status scivr_accumulate_spectrum_fft(scivr_ctx *ctx, void *stream)
+{
+    CHECK_CTX(ctx);
+    if (!ctx->have_initial || ctx->steps_done != ctx->n_steps)
+        return ctx_fail(ctx, SCIVR_ESTATE, "accumulate needs a fully propagated batch (%d of %d steps)", ctx->steps_done,
+                    ctx->n_steps);
+    if (ctx->accumulated) return ctx_fail(ctx, SCIVR_ESTATE, "batch already accumulated");
+    const int lg = fft_log2_length(ctx->nt);
+    if (lg > FFT_MAX_LOG2)
+        return ctx_fail(ctx, SCIVR_EUNSUPPORTED, "the FFT accumulation holds at most %d steps (the problem has %d)",
+                        1 << (FFT_MAX_LOG2 - 1), ctx->n_steps);
+    const int L = 1 << lg;
+    if (!ctx->d_fft_part) {  // scratch for the longest sequence the library takes, on first use
+        const int nwg = 256, Lmax = 1 << FFT_MAX_LOG2;
+        double *part = nullptr, *S = nullptr;
+        double2 *pcorr = nullptr, *corr = nullptr, *C = nullptr;
+        const bool ok = dalloc(&part, (int64_t)nwg * Lmax) == hipSuccess && dalloc(&S, Lmax) == hipSuccess &&
+                        dalloc(&pcorr, nwg) == hipSuccess && dalloc(&corr, 1) == hipSuccess &&
+                        dalloc(&C, Lmax / 2 + 1) == hipSuccess;
+        if (!ok) {
+            for (void *q : {(void *)part, (void *)S, (void *)pcorr, (void *)corr, (void *)C})
+                if (q) (void)hipFree(q);
+            (void)hipGetLastError();
+            return ctx_fail(ctx, SCIVR_ENOMEM, "FFT scratch allocation failed");
+        }
+        ctx->fft_nwg = nwg;
+        ctx->d_fft_part = part;
+        ctx->d_fft_S = S;
+        ctx->d_fft_pcorr = pcorr;
+        ctx->d_fft_corr = corr;
+        ctx->d_fft_C = C;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    HIPCALL(ctx, launch_weights(ctx->d_prob, ctx->F, ctx->d_scal + SC_GOOD * ctx->npad,
+                                ctx->d_scal + SC_ESCALE * ctx->npad, ctx->d_logrho, ctx->d_p0, ctx->d_q0,
+                                ctx->husimi_batch, ctx->n_traj, ctx->npad, ctx->d_weight, ctx->d_goodw_row,
+                                ctx->d_ngood, ctx->d_goodw, s));
+    FftArgs a;
+    a.amp = ctx->d_amp;
+    a.amp16 = ctx->d_amp16;
+    a.plane = (int64_t)ctx->nt16 * ctx->npad;
+    a.weight = ctx->d_weight;
+    a.part = ctx->d_fft_part;
+    a.part_corr = ctx->d_fft_pcorr;
+    a.n = ctx->n_traj;
+    a.npad = ctx->npad;
+    a.nt = ctx->nt;
+    a.nwg = ctx->fft_nwg;
+    a.fold = (L == 2 * (ctx->nt - 1)) ? 1 : 0;
+    {
+        Timed tm(ctx, s, 2);
+        HIPCALL(ctx, launch_fourier_fft(a, ctx->precision == SCIVR_PRECISION_MIXED, ctx->e_min,
+                                        (ctx->e_max - ctx->e_min) / (double)(ctx->n_energies - 1), ctx->dt,
+                                        ctx->n_energies, ctx->d_fft_S, ctx->d_fft_corr, ctx->d_fft_C, ctx->d_total,
+                                        s));
+        tm.done();
+    }
+    ctx->n_total += ctx->n_traj;
+    ctx->accumulated = true;
+    ctx->contrib_valid = false;
     return SCIVR_OK;
 }
 
@@ -542,6 +607,8 @@ scivr_status scivr_read_contributions(scivr_ctx *ctx, double *c)
     CHECK_CTX(ctx);
     if (!c) return ctx_fail(ctx, SCIVR_EINVAL, "null output");
     if (!ctx->accumulated) return ctx_fail(ctx, SCIVR_ESTATE, "batch not accumulated");
+    if (!ctx->contrib_valid)
+        return ctx_fail(ctx, SCIVR_ESTATE, "the FFT accumulation produces no per-trajectory contributions");
     HIPCALL(ctx, hipDeviceSynchronize());
     HIPCALL(ctx, hipMemcpy(c, ctx->d_contrib, sizeof(double) * ctx->n_traj, hipMemcpyDeviceToHost));
     return SCIVR_OK;

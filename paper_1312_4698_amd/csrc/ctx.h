@@ -41,6 +41,11 @@ struct scivr_ctx {
     int64_t n_traj = 0;      // current batch size
     int32_t steps_done = 0;
     bool have_initial = false, accumulated = false;
+    bool contrib_valid = false;  // the last accumulation produced per-trajectory contributions (the GEMM does)
+    // FFT-autocorrelation accumulation: scratch allocated on first use
+    int32_t fft_nwg = 0;
+    double *d_fft_part = nullptr, *d_fft_S = nullptr;
+    double2 *d_fft_pcorr = nullptr, *d_fft_corr = nullptr, *d_fft_C = nullptr;
     int64_t n_total = 0;     // trajectories accumulated so far
 
     bool device_error = false;

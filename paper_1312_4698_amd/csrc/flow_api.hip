@@ -492,6 +492,8 @@ scivr_status scivr_flow_train_on_batch(scivr_flow *f, int32_t epochs, int32_t ba
     CHECK_FLOW(f);
     scivr_ctx *ctx = f->ctx;
     if (!ctx->accumulated) return FLOW_FAIL(f, SCIVR_ESTATE, "the context's batch has not been accumulated");
+    if (!ctx->contrib_valid)
+        return FLOW_FAIL(f, SCIVR_ESTATE, "the batch was accumulated without per-trajectory contributions (FFT form)");
     if (epochs < 0 || batch < 1 || !(lr >= 0.f) || !std::isfinite(lr))
         return FLOW_FAIL(f, SCIVR_EINVAL, "bad epochs %d / batch %d / lr %g", epochs, batch, (double)lr);
     hipStream_t s = (hipStream_t)stream;

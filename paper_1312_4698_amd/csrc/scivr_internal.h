@@ -66,6 +66,23 @@ struct GemmF16Args {
     double e_min, de, dt;
 };
 
+// FFT-autocorrelation form of the Fourier accumulation: sequences of length
+// L = 2^lg >= 2 (n_t - 1), lg <= FFT_MAX_LOG2 (the whole sequence in LDS).
+constexpr int FFT_MAX_LOG2 = 13;
+struct FftArgs {
+    const double2 *amp;      // FP64 form: [nt_alloc][npad]
+    const _Float16 *amp16;   // mixed form: 4 planes [nt16 / 8][npad][8]
+    int64_t plane;
+    const double *weight;    // [npad] w_j good_j (2^-2 escale_j in the mixed form)
+    double *part;            // [nwg][L] per-workgroup sums of w_j |X_j[m]|^2, bit-reversed bins
+    double2 *part_corr;      // [nwg] per-workgroup sums of the folded lag
+    int64_t n, npad;
+    int32_t nt, nwg, fold;   // fold: L == 2 (n_t - 1), lag L/2 summed directly
+};
+int fft_log2_length(int nt);
+hipError_t launch_fourier_fft(const FftArgs &a, bool mixed, double e_min, double de, double dt, int K, double *S,
+                              double2 *corr, double2 *C, double *total, hipStream_t st);
+
 struct GemmArgs {
     const double2 *amp;     // [nt_pad][npad]
     const double2 *phase;   // [nt_pad][kpad]

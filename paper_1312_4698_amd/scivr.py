@@ -38,7 +38,8 @@ _STATUS = {EINVAL: "SCIVR_EINVAL", ENOMEM: "SCIVR_ENOMEM", EDEVICE: "SCIVR_EDEVI
 # Every symbol the header declares.
 EXPORTED = (
     "scivr_abi_version", "scivr_create", "scivr_destroy", "scivr_last_error", "scivr_sample_husimi",
-    "scivr_set_initial", "scivr_propagate", "scivr_accumulate_spectrum", "scivr_read_spectrum",
+    "scivr_set_initial", "scivr_propagate", "scivr_accumulate_spectrum", "scivr_accumulate_spectrum_fft",
+    "scivr_read_spectrum",
     "scivr_reset_spectrum", "scivr_batch_info", "scivr_read_initial", "scivr_read_state",
     "scivr_read_amplitudes", "scivr_read_contributions", "scivr_timing_enable", "scivr_kernel_times",
     "scivr_flow_create", "scivr_flow_destroy", "scivr_flow_param_count", "scivr_flow_set_params",
@@ -97,6 +98,7 @@ def load() -> ctypes.CDLL:
         "scivr_set_initial": (i32, [v, i64, v, v, v, i32, v]),
         "scivr_propagate": (i32, [v, i32, i32, v]),
         "scivr_accumulate_spectrum": (i32, [v, v]),
+        "scivr_accumulate_spectrum_fft": (i32, [v, v]),
         "scivr_read_spectrum": (i32, [v, v, ctypes.POINTER(i64), ctypes.POINTER(i64)]),
         "scivr_reset_spectrum": (i32, [v, v]),
         "scivr_batch_info": (i32, [v, ctypes.POINTER(i64), ctypes.POINTER(i32)]),
@@ -224,6 +226,10 @@ class Context:
 
     def accumulate(self, stream=None):
         self._check(self._lib.scivr_accumulate_spectrum(self._h, _stream(stream)))
+
+    def accumulate_fft(self, stream=None):
+        """The batch's spectrum by the exact FFT-autocorrelation form (``scivr_accumulate_spectrum_fft``)."""
+        self._check(self._lib.scivr_accumulate_spectrum_fft(self._h, _stream(stream)))
 
     def read_spectrum(self):
         """(I [K], n_good, n_total); I is zero when n_good == 0."""
