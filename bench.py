@@ -151,6 +151,32 @@ def run_form(scivr, torch, prob, n, steps, warmup, seed0=1000, chunk=0, energy=N
     return {"wall": wall, "kt": kt, "I": I, "n_good": n_good, "n_total": n_total, "joules": joules}
 
 
+def fft_form(scivr, torch, prob, n, seed=4321):
+    """The Fourier step of one batch by the GEMM and by the exact FFT
+    autocorrelation form, on identical trajectories: launch times and the
+    spectra's largest relative difference."""
+    stream = torch.cuda.current_stream()
+    ctx = scivr.Context(prob, max_traj=n)
+    res = {}
+    for form in ("gemm", "fft"):
+        ctx.reset_spectrum(stream=stream)
+        ctx.sample_husimi(seed=seed, n_traj=n, stream=stream)
+        ctx.propagate(0, prob.n_steps, stream=stream)
+        ctx.timing(True)
+        if form == "fft":
+            ctx.accumulate_fft(stream=stream)
+        else:
+            ctx.accumulate(stream=stream)
+        kt = ctx.kernel_times()
+        I, _, _ = ctx.read_spectrum()
+        res[form] = (kt["fourier"][1], I)
+        print(f"[bench] {prob.name} Fourier step by {form}: {kt['fourier'][1]:.1f} ms", file=sys.stderr, flush=True)
+    ctx.close()
+    (g_ms, Ig), (f_ms, If) = res["gemm"], res["fft"]
+    return {"gemm_ms": g_ms, "fft_ms": f_ms, "speedup": g_ms / f_ms,
+            "max_rel_diff": float(np.max(np.abs(If - Ig)) / np.max(np.abs(Ig)))}
+
+
 def _peak_error_cm(peaks, inputs, E, T, ref_peaks, I):
     """Largest peak shift (cm^-1) of I against the reference peaks; inf if a peak is missing."""
     pt = peaks.find_peaks(E, I, T)
@@ -255,6 +281,8 @@ def main():
     ap.add_argument("--n-traj", type=int, default=0, help="override the trajectory count")
     ap.add_argument("--cpu-sample", type=int, default=512, help="oracle trajectories for the CPU baseline (0: skip)")
     ap.add_argument("--learned", type=int, default=1, help="run the learned-proposal study (1) or not (0)")
+    ap.add_argument("--fft", type=int, default=1,
+                    help="also time the exact FFT-autocorrelation Fourier step against the GEMM (1) or not (0)")
     ap.add_argument("--chunk", type=int, default=0,
                     help="propagate in calls of this many time steps, printing progress (0: one call)")
     ap.add_argument("--copy-calibration", type=int, default=0,
@@ -402,6 +430,22 @@ def main():
                      "including its training batch and training time; equal_variance_speedup = (plain/learned "
                      "spectrum variance at equal N) x (mixed/plain throughput)"),
         }
+    if args.fft:
+        # a separate wall-time line: the Fourier step of one batch of each form
+        # by the FFT autocorrelation against the GEMM (not part of `value`)
+        forms = [(prob, "main")] + ([(inputs.workload(args.plain)[0], "plain_fp64")] if args.plain else [])
+        out["fft_fourier"] = {}
+        for fp, key in forms:
+            if fp.n_steps > 4096:
+                out["fft_fourier"][key] = {"skipped": "the FFT form holds at most 4096 steps"}
+                continue
+            r = fft_form(scivr, torch, fp, n)
+            tr_ms = (kt if key == "main" else plain["kt"])["trajectory"][1] / args.steps  # per pass
+            r["value_with_fft"] = traj_steps / ((tr_ms + r["fft_ms"]) / 1e3)
+            out["fft_fourier"][key] = r
+        out["fft_fourier"]["note"] = ("exact FFT autocorrelation form of the Fourier step (scivr_accumulate_spectrum_fft) "
+                                      "on one batch of identical trajectories; value_with_fft = trajectory-steps/s "
+                                      "with the measured trajectory kernel time and the FFT form in place of the GEMM")
     if args.cpu_sample > 0:
         print(f"[bench] cpu baseline: oracle on {args.cpu_sample} trajectories", file=sys.stderr, flush=True)
         pprob = prob.replace(precision=inputs.PRECISION_FP64)

@@ -15,7 +15,8 @@
 // Kernels:
 //  * fft_power_kernel: one workgroup per trajectory at a time, the whole
 //    length-L FP64 sequence in LDS (L <= 8192: 128 KB), an in-place radix-2
-//    decimation-in-frequency FFT (bit-reversed output), and w_j |X_j[m]|^2
+//    decimation-in-frequency FFT (bit-reversed output) with its twiddles in
+//    registers, and w_j |X_j[m]|^2
 //    accumulated in registers at fixed bins per thread over the workgroup's
 //    trajectories; concurrently running workgroups of one XCD take
 //    consecutive trajectories, so the 128-byte lines of the time-major
@@ -45,14 +46,30 @@ template <int LOG2L, bool MIXED>
 __global__ void __launch_bounds__(FFT_THREADS, 1) fft_power_kernel(FftArgs G)
 {
     constexpr int L = 1 << LOG2L;
-    constexpr int PER = L / FFT_THREADS > 0 ? L / FFT_THREADS : 1;  // bins per thread
+    constexpr int PER = L / FFT_THREADS > 0 ? L / FFT_THREADS : 1;      // bins per thread
+    constexpr int NB = L / 2 / FFT_THREADS > 0 ? L / 2 / FFT_THREADS : 1;  // butterflies per thread per pass
     __shared__ double2 X[L];
-    __shared__ double2 tw[L / 4 > 0 ? L / 4 : 1];  // e^{-2 pi i k / L}, k < L / 4
     const int t = threadIdx.x;
-    for (int k = t; k < L / 4; k += FFT_THREADS) {
-        double s, c;
-        sincospi(2.0 * (double)k / (double)L, &s, &c);
-        tw[k] = make_double2(c, -s);
+
+    // Twiddles in registers: in the pass with half-span h (stride L / (2h) of
+    // the exponent) butterfly m of this thread, number b = t + 256 m, has
+    // exponent ((b mod h) L / (2h)), which repeats with period max(1, h / 256)
+    // in m.  Computed once; reading them from an LDS table instead costs bank
+    // conflicts of up to 32 ways in the middle passes.
+    double2 tw[LOG2L][NB];
+#pragma unroll
+    for (int s = 0; s < LOG2L; ++s) {
+        const int h = L >> (s + 1);
+        const int rep = h > FFT_THREADS ? h / FFT_THREADS : 1;  // distinct values in m
+#pragma unroll
+        for (int m = 0; m < NB; ++m) {
+            if (m >= rep) break;
+            const int b = t + FFT_THREADS * m;
+            const int e = (b & (h - 1)) << s;  // < L / 2
+            double sn, cs;
+            sincospi(2.0 * (double)e / (double)L, &sn, &cs);
+            tw[s][m] = make_double2(cs, -sn);
+        }
     }
 
     double acc[PER];
@@ -65,9 +82,11 @@ __global__ void __launch_bounds__(FFT_THREADS, 1) fft_power_kernel(FftArgs G)
     const int nwg = gridDim.x;
     const int xcd = blockIdx.x % 8, slot = blockIdx.x / 8, per = nwg / 8;
     const int nt = G.nt;
+    auto traj_of = [&](int64_t it) { return (it * 8 + xcd) * per + slot; };
+
     for (int64_t it = 0;; ++it) {
-        const int64_t j = (it * 8 + xcd) * per + slot;
         if ((it * 8) * per >= G.n) break;  // every workgroup leaves after the same round
+        const int64_t j = traj_of(it);
         const bool have = j < G.n;
         const double w = have ? G.weight[j] : 0.0;
         __syncthreads();  // the previous trajectory's bins have been read
@@ -77,10 +96,10 @@ __global__ void __launch_bounds__(FFT_THREADS, 1) fft_power_kernel(FftArgs G)
         } else {
             // FP16 hi/lo planes [t / 8][trajectory][t % 8]: one 16-byte chunk per plane per 8 samples
             typedef _Float16 h8 __attribute__((ext_vector_type(8)));
-            for (int b = t; b < L / 8; b += FFT_THREADS) {
+            for (int bch = t; bch < L / 8; bch += FFT_THREADS) {
                 h8 rh = (h8)0, rl = (h8)0, ih = (h8)0, il = (h8)0;
-                if (have && 8 * b < nt) {
-                    const _Float16 *a = G.amp16 + ((int64_t)b * G.npad + j) * 8;
+                if (have && 8 * bch < nt) {
+                    const _Float16 *a = G.amp16 + ((int64_t)bch * G.npad + j) * 8;
                     rh = *(const h8 *)(a);
                     rl = *(const h8 *)(a + G.plane);
                     ih = *(const h8 *)(a + 2 * G.plane);
@@ -88,7 +107,7 @@ __global__ void __launch_bounds__(FFT_THREADS, 1) fft_power_kernel(FftArgs G)
                 }
 #pragma unroll
                 for (int s = 0; s < 8; ++s) {
-                    const int c = 8 * b + s;
+                    const int c = 8 * bch + s;
                     const double re = (double)((float)rh[s] + (float)rl[s]);
                     const double im = (double)((float)ih[s] + (float)il[s]);
                     X[c] = (c < nt) ? make_double2(re, im) : make_double2(0.0, 0.0);
@@ -102,17 +121,20 @@ __global__ void __launch_bounds__(FFT_THREADS, 1) fft_power_kernel(FftArgs G)
             corr.y += w * (a.y * b0.x - a.x * b0.y);
         }
         // radix-2 decimation in frequency, in place
-#pragma unroll 1
-        for (int h = L / 2, tstep = 1; h >= 1; h >>= 1, tstep <<= 1) {
-            for (int b = t; b < L / 2; b += FFT_THREADS) {
-                const int pos = b & (h - 1);
-                const int i0 = ((b - pos) << 1) + pos, i1 = i0 + h;
-                const double2 u = X[i0], v = X[i1];
-                const int e = pos * tstep;  // twiddle exponent, < L / 2
-                const double2 q = tw[e & (L / 4 - 1 > 0 ? L / 4 - 1 : 0)];
-                const double2 wv = (e < L / 4) ? q : make_double2(q.y, -q.x);  // times -i
-                X[i0] = make_double2(u.x + v.x, u.y + v.y);
-                X[i1] = cmul(make_double2(u.x - v.x, u.y - v.y), wv);
+#pragma unroll
+        for (int s = 0; s < LOG2L; ++s) {
+            const int h = L >> (s + 1);
+#pragma unroll
+            for (int m = 0; m < NB; ++m) {
+                const int b = t + FFT_THREADS * m;
+                if (b < L / 2) {
+                    const int pos = b & (h - 1);
+                    const int i0 = ((b - pos) << 1) + pos, i1 = i0 + h;
+                    const double2 u = X[i0], v = X[i1];
+                    X[i0] = make_double2(u.x + v.x, u.y + v.y);
+                    const int rep = h > FFT_THREADS ? h / FFT_THREADS : 1;
+                    X[i1] = cmul(make_double2(u.x - v.x, u.y - v.y), tw[s][m % rep]);
+                }
             }
             __syncthreads();
         }
