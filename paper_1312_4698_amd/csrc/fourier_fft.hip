@@ -15,8 +15,8 @@
 // Kernels:
 //  * fft_power_kernel: one workgroup per trajectory at a time, the whole
 //    length-L FP64 sequence in LDS (L <= 8192: 128 KB), an in-place radix-2
-//    decimation-in-frequency FFT (bit-reversed output) with its twiddles in
-//    registers, and w_j |X_j[m]|^2
+//    decimation-in-frequency FFT with the passes fused in pairs and the
+//    twiddles in registers (bit-reversed output), and w_j |X_j[m]|^2
 //    accumulated in registers at fixed bins per thread over the workgroup's
 //    trajectories; concurrently running workgroups of one XCD take
 //    consecutive trajectories, so the 128-byte lines of the time-major
@@ -47,28 +47,35 @@ __global__ void __launch_bounds__(FFT_THREADS, 1) fft_power_kernel(FftArgs G)
 {
     constexpr int L = 1 << LOG2L;
     constexpr int PER = L / FFT_THREADS > 0 ? L / FFT_THREADS : 1;      // bins per thread
-    constexpr int NB = L / 2 / FFT_THREADS > 0 ? L / 2 / FFT_THREADS : 1;  // butterflies per thread per pass
     __shared__ double2 X[L];
     const int t = threadIdx.x;
 
-    // Twiddles in registers: in the pass with half-span h (stride L / (2h) of
-    // the exponent) butterfly m of this thread, number b = t + 256 m, has
-    // exponent ((b mod h) L / (2h)), which repeats with period max(1, h / 256)
-    // in m.  Computed once; reading them from an LDS table instead costs bank
-    // conflicts of up to 32 ways in the middle passes.
-    double2 tw[LOG2L][NB];
+    // Passes are fused in pairs (radix 2^2): thread group g = t + 256 m takes
+    // the four elements i0, i0 + q, i0 + h, i0 + h + q (i0 = (g / q) 2h + g mod q)
+    // through the passes of half-spans h and q = h / 2, which is exactly those
+    // two radix-2 passes (output stays bit-reversed).  Its twiddles, with
+    // p = g mod q and exponent step ts = L / (2h): W^{p ts}, W^{(p + q) ts} for
+    // the first pass and W^{2 p ts} for the second, repeat with period
+    // max(1, q / 256) in m.  They are computed once into registers; reading
+    // them from an LDS table costs bank conflicts of up to 32 ways.
+    constexpr int NPAIR = LOG2L / 2;
+    constexpr int NG = L / 4 / FFT_THREADS > 0 ? L / 4 / FFT_THREADS : 1;  // groups per thread per pair
+    double2 tw1[NPAIR > 0 ? NPAIR : 1][NG], tw2[NPAIR > 0 ? NPAIR : 1][NG], tw3[NPAIR > 0 ? NPAIR : 1][NG];
 #pragma unroll
-    for (int s = 0; s < LOG2L; ++s) {
-        const int h = L >> (s + 1);
-        const int rep = h > FFT_THREADS ? h / FFT_THREADS : 1;  // distinct values in m
+    for (int pr = 0; pr < NPAIR; ++pr) {
+        const int sft = 2 * pr, h = L >> (sft + 1), q = h >> 1;
+        const int rep = q > FFT_THREADS ? q / FFT_THREADS : 1;
 #pragma unroll
-        for (int m = 0; m < NB; ++m) {
+        for (int m = 0; m < NG; ++m) {
             if (m >= rep) break;
-            const int b = t + FFT_THREADS * m;
-            const int e = (b & (h - 1)) << s;  // < L / 2
+            const int p = (t + FFT_THREADS * m) & (q - 1);
             double sn, cs;
-            sincospi(2.0 * (double)e / (double)L, &sn, &cs);
-            tw[s][m] = make_double2(cs, -sn);
+            sincospi(2.0 * (double)(p << sft) / (double)L, &sn, &cs);
+            tw1[pr][m] = make_double2(cs, -sn);
+            sincospi(2.0 * (double)((p + q) << sft) / (double)L, &sn, &cs);
+            tw2[pr][m] = make_double2(cs, -sn);
+            sincospi(2.0 * (double)(p << (sft + 1)) / (double)L, &sn, &cs);
+            tw3[pr][m] = make_double2(cs, -sn);
         }
     }
 
@@ -120,21 +127,36 @@ __global__ void __launch_bounds__(FFT_THREADS, 1) fft_power_kernel(FftArgs G)
             corr.x += w * (a.x * b0.x + a.y * b0.y);
             corr.y += w * (a.y * b0.x - a.x * b0.y);
         }
-        // radix-2 decimation in frequency, in place
+        // radix-2 decimation in frequency, in place, two passes at a time
 #pragma unroll
-        for (int s = 0; s < LOG2L; ++s) {
-            const int h = L >> (s + 1);
+        for (int pr = 0; pr < NPAIR; ++pr) {
+            const int h = L >> (2 * pr + 1), q = h >> 1, lq = LOG2L - 2 * pr - 2;  // q = 2^lq
+            const int rep = q > FFT_THREADS ? q / FFT_THREADS : 1;
 #pragma unroll
-            for (int m = 0; m < NB; ++m) {
-                const int b = t + FFT_THREADS * m;
-                if (b < L / 2) {
-                    const int pos = b & (h - 1);
-                    const int i0 = ((b - pos) << 1) + pos, i1 = i0 + h;
-                    const double2 u = X[i0], v = X[i1];
-                    X[i0] = make_double2(u.x + v.x, u.y + v.y);
-                    const int rep = h > FFT_THREADS ? h / FFT_THREADS : 1;
-                    X[i1] = cmul(make_double2(u.x - v.x, u.y - v.y), tw[s][m % rep]);
+            for (int m = 0; m < NG; ++m) {
+                const int g = t + FFT_THREADS * m;
+                if (g < L / 4) {
+                    const int p = g & (q - 1);
+                    const int i0 = ((g >> lq) << (lq + 2)) + p;
+                    const double2 a = X[i0], b = X[i0 + q], c = X[i0 + h], d = X[i0 + h + q];
+                    const double2 a1 = make_double2(a.x + c.x, a.y + c.y);
+                    const double2 c1 = cmul(make_double2(a.x - c.x, a.y - c.y), tw1[pr][m % rep]);
+                    const double2 b1 = make_double2(b.x + d.x, b.y + d.y);
+                    const double2 d1 = cmul(make_double2(b.x - d.x, b.y - d.y), tw2[pr][m % rep]);
+                    const double2 w3 = tw3[pr][m % rep];
+                    X[i0] = make_double2(a1.x + b1.x, a1.y + b1.y);
+                    X[i0 + q] = cmul(make_double2(a1.x - b1.x, a1.y - b1.y), w3);
+                    X[i0 + h] = make_double2(c1.x + d1.x, c1.y + d1.y);
+                    X[i0 + h + q] = cmul(make_double2(c1.x - d1.x, c1.y - d1.y), w3);
                 }
+            }
+            __syncthreads();
+        }
+        if constexpr (LOG2L % 2 == 1) {  // the last pass (half-span 1, twiddle 1) alone
+            for (int b = t; b < L / 2; b += FFT_THREADS) {
+                const double2 u = X[2 * b], v = X[2 * b + 1];
+                X[2 * b] = make_double2(u.x + v.x, u.y + v.y);
+                X[2 * b + 1] = make_double2(u.x - v.x, u.y - v.y);
             }
             __syncthreads();
         }
