@@ -84,7 +84,7 @@ __global__ void __launch_bounds__(FFT_THREADS, 1) fft_power_kernel(FftArgs G)
     for (int r = 0; r < PER; ++r) acc[r] = 0.0;
     double2 corr = make_double2(0.0, 0.0);
 
-    // workgroup wg runs on XCD wg % 8 as local slot wg / 8; in round `it` the
+    // workgroup wg runs on XCD wg % 8 as local slot wg / 8; in iteration `it` the
     // XCD's slots take trajectories [(it * 8 + xcd) * per, +per)
     const int nwg = gridDim.x;
     const int xcd = blockIdx.x % 8, slot = blockIdx.x / 8, per = nwg / 8;
@@ -92,7 +92,7 @@ __global__ void __launch_bounds__(FFT_THREADS, 1) fft_power_kernel(FftArgs G)
     auto traj_of = [&](int64_t it) { return (it * 8 + xcd) * per + slot; };
 
     for (int64_t it = 0;; ++it) {
-        if ((it * 8) * per >= G.n) break;  // every workgroup leaves after the same round
+        if ((it * 8) * per >= G.n) break;  // every workgroup leaves after the same iteration
         const int64_t j = traj_of(it);
         const bool have = j < G.n;
         const double w = have ? G.weight[j] : 0.0;
