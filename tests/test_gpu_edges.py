@@ -152,3 +152,47 @@ def test_flow_misuse_errors(scivr):
         fl.set_params(np.zeros(fl.n_params + 1))
     fl.close()
     ctx.close()
+
+
+@pytest.mark.parametrize("precision", [inputs.PRECISION_FP64, inputs.PRECISION_MIXED])
+def test_amplitudes_zero_from_the_flagging_step(scivr, precision):
+    """F = 9 finishes amplitudes in batches of eight time samples.  A
+    trajectory flagged at step s must have non-zero amplitudes before sample s
+    and zeros from it on, wherever s falls in a batch.  The flagging steps come
+    from propagating one step per call and reading the sticky flag after each;
+    the single-call run must give bit-identical amplitudes."""
+    S = scivr
+    ns, n = 800, 70
+    # a tolerance at the median of the largest |det(M)^2 - 1| over 800 steps,
+    # so trajectories turn bad at scattered steps
+    prob = inputs.morse_quartic(9, 9, n_steps=ns, n_energies=64, e_max=0.1, det_tol=3e-13, precision=precision)
+    c1 = S.Context(prob, max_traj=n)
+    c1.sample_husimi(21, n)
+    first_bad = np.full(n, -1)
+    for s in range(ns):
+        c1.propagate(s, s + 1)
+        g = c1.read_state()["good"]
+        first_bad[(g == 0) & (first_bad < 0)] = s + 1
+    a1 = c1.read_amplitudes(0, n)
+    c2 = S.Context(prob, max_traj=n)
+    c2.sample_husimi(21, n)
+    c2.propagate(0, ns)
+    a2 = c2.read_amplitudes(0, n)
+    assert np.array_equal(a1, a2)
+    mag = np.abs(a2)
+    # FP16 planes can underflow to an exact zero where the overlap has decayed,
+    # so only the FP64 form checks that the samples before the flag are non-zero
+    exact = precision == inputs.PRECISION_FP64
+    mid = 0
+    for j in range(n):
+        if first_bad[j] < 0:
+            assert not exact or np.all(mag[j] > 0), j
+        else:
+            fb = first_bad[j]
+            assert np.all(mag[j, fb:] == 0), (j, fb)
+            assert not exact or np.all(mag[j, :fb] > 0), (j, fb)
+            mid += fb % 8 != 0
+    _say(f"[flag step] {precision}: {np.sum(first_bad >= 0)} of {n} flagged, {mid} inside a batch of eight")
+    assert mid >= 3
+    c1.close()
+    c2.close()
