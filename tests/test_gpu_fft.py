@@ -133,3 +133,26 @@ def test_fft_form_state_errors(scivr):
         c2.accumulate_fft()                       # L would be 16384
     assert e.value.status == S.EUNSUPPORTED
     c2.close()
+
+
+def test_fft_form_adds_into_the_running_totals(scivr):
+    # two batches, the first by the GEMM and the second by the FFT form, give
+    # the estimate of two GEMM batches
+    prob = inputs.morse_quartic(3, 3, n_steps=256, n_energies=100, e_max=0.06)
+    n = 80
+    ref = scivr.Context(prob, max_traj=n)
+    mix = scivr.Context(prob, max_traj=n)
+    for b, first in enumerate((0, n)):
+        for ctx, fft in ((ref, False), (mix, b == 1)):
+            ctx.sample_husimi(17, n, first)
+            ctx.propagate(0, prob.n_steps)
+            if fft:
+                ctx.accumulate_fft()
+            else:
+                ctx.accumulate()
+    Ir, ngr, ntr = ref.read_spectrum()
+    Im, ngm, ntm = mix.read_spectrum()
+    assert ntr == ntm == 2 * n and ngr == ngm
+    assert np.max(np.abs(Im - Ir)) < 1e-11 * np.max(np.abs(Ir))
+    ref.close()
+    mix.close()
