@@ -13,7 +13,8 @@
 // is summed directly.  The result equals the GEMM's to rounding.
 //
 // Kernels:
-//  * fft_power_kernel: one workgroup per trajectory at a time, the whole
+//  * fft_power_kernel: one workgroup of 512 threads (two waves per SIMD) per
+//    trajectory at a time, the whole
 //    length-L FP64 sequence in LDS (L <= 8192: 128 KB), an in-place radix-2
 //    decimation-in-frequency FFT with the passes fused in pairs and the
 //    twiddles in registers (bit-reversed output), and w_j |X_j[m]|^2
@@ -33,7 +34,7 @@
 namespace scivr {
 namespace {
 
-constexpr int FFT_THREADS = 256;
+constexpr int FFT_THREADS = 512;
 
 __device__ inline double2 cmul(double2 a, double2 b)
 {
@@ -50,13 +51,13 @@ __global__ void __launch_bounds__(FFT_THREADS, 1) fft_power_kernel(FftArgs G)
     __shared__ double2 X[L];
     const int t = threadIdx.x;
 
-    // Passes are fused in pairs (radix 2^2): thread group g = t + 256 m takes
+    // Passes are fused in pairs (radix 2^2): thread group g = t + T m (T threads) takes
     // the four elements i0, i0 + q, i0 + h, i0 + h + q (i0 = (g / q) 2h + g mod q)
     // through the passes of half-spans h and q = h / 2, which is exactly those
     // two radix-2 passes (output stays bit-reversed).  Its twiddles, with
     // p = g mod q and exponent step ts = L / (2h): W^{p ts}, W^{(p + q) ts} for
     // the first pass and W^{2 p ts} for the second, repeat with period
-    // max(1, q / 256) in m.  They are computed once into registers; reading
+    // max(1, q / T) in m.  They are computed once into registers; reading
     // them from an LDS table costs bank conflicts of up to 32 ways.
     constexpr int NPAIR = LOG2L / 2;
     constexpr int NG = L / 4 / FFT_THREADS > 0 ? L / 4 / FFT_THREADS : 1;  // groups per thread per pair
