@@ -47,6 +47,8 @@ def _spectrum(S, prob, seed, n, fft):
     (3, 65, 1, 40, 0.06),        # one step
     (9, 140, 200, 129, 0.1),     # L = 512 > 400
     (9, 70, 256, 100, 0.1),      # L = 512 = 2 (n_t - 1)
+    (17, 40, 150, 100, 0.15),    # amplitudes of the one-wave-per-trajectory kernel
+    (30, 24, 128, 128, 0.2),     # L = 256 = 2 (n_t - 1)
 ])
 def test_fft_form_matches_gemm_form(scivr, F, n, ns, K, emax):
     _say(f"[fft] F={F} n={n} steps={ns} K={K}")
@@ -88,10 +90,10 @@ def test_fft_form_longest_sequence(scivr):
     c2.close()
 
 
-def test_fft_form_mixed_precision(scivr):
-    prob = inputs.morse_quartic(9, 9, n_steps=256, n_energies=160, e_max=0.1,
+@pytest.mark.parametrize("F,n", [(9, 140), (30, 24)])
+def test_fft_form_mixed_precision(scivr, F, n):
+    prob = inputs.morse_quartic(F, F, n_steps=256, n_energies=160, e_max=0.1 if F < 17 else 0.2,
                                 precision=inputs.PRECISION_MIXED)
-    n = 140
     c1, Ig, _, _ = _spectrum(scivr, prob, 5, n, fft=False)
     c2, If, _, _ = _spectrum(scivr, prob, 5, n, fft=True)
     rel = np.max(np.abs(If - Ig)) / np.max(np.abs(Ig))
