@@ -5,8 +5,11 @@ leg of the benchmark are the only callers.  The product path never imports
 this module.  It takes plain numpy arrays (the problem definition and the
 initial conditions) and shares no code with the HIP library.
 
-Every function here only marshals arguments; the arithmetic is in the C file,
-which cites the paper's equations.
+The functions here marshal arguments to the C files, which hold the method's
+arithmetic and cite the paper's equations, with one exception: good_weight,
+the importance-weighted good count of reading R15 (a few lines of numpy,
+documented where it is defined).  precision_probe.c (same library) holds the
+binary128 and long-double checks of what the stability monitor measures.
 """
 from __future__ import annotations
 
@@ -20,6 +23,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "scivr_oracle.c")
+_SRCS = [_SRC, os.path.join(_HERE, "precision_probe.c")]
 _LIB = os.environ.get("SCIVR_ORACLE_SO") or os.path.join(_HERE, "libscivr_oracle.so")
 
 # Offsets of the scalar part of the per-trajectory state (after p and q).
@@ -28,10 +32,10 @@ ST_S, ST_THETA, ST_RPREV, ST_PHI, ST_GOOD, ST_DETM, ST_MAXDEV, ST_STEP, ST_NSCAL
 
 def build(force: bool = True) -> str:
     """Compile the oracle with gcc (-O2, no fast-math, no FP contraction, OpenMP)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < max(os.path.getmtime(f) for f in _SRCS):
         tmp = _LIB + ".tmp"
         cmd = ["gcc", "-O2", "-fno-fast-math", "-ffp-contract=off", "-fopenmp", "-shared", "-fPIC",
-               "-std=c11", "-Wall", "-o", tmp, _SRC, "-lm"]
+               "-std=gnu11", "-Wall", "-o", tmp, *_SRCS, "-lquadmath", "-lm"]
         subprocess.run(cmd, check=True)
         os.replace(tmp, _LIB)
     return _LIB
@@ -63,7 +67,7 @@ _lib = None
 def _load():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < max(os.path.getmtime(f) for f in _SRCS):
             build(force=True)
         lib = ctypes.CDLL(_LIB)
         P = ctypes.POINTER(_Problem)
@@ -88,6 +92,8 @@ def _load():
         lib.orc_run.argtypes = [P, ctypes.c_int64, d, d, d, d, ctypes.POINTER(ctypes.c_int64), d, d, d,
                                 ctypes.c_int32]
         lib.orc_normalise.argtypes = [P, d, ctypes.c_int64, d]
+        lib.orc_monitor_probe.restype = ctypes.c_int
+        lib.orc_monitor_probe.argtypes = [P, d, d, ctypes.c_int32, ctypes.c_int32, d]
         _lib = lib
     return _lib
 
@@ -330,3 +336,22 @@ def good_weight(prob, p0, q0, logrho, good) -> float:
     log_h = -F * np.log(2.0 * np.pi) - 0.5 * np.sum(xi2 + eta2, axis=0)
     r = np.exp(log_h - np.asarray(logrho, dtype=np.float64))
     return float(np.sum(r[np.asarray(good, dtype=bool)]))
+
+
+def monitor_probe(prob, p0, q0, n_steps: int, every: int) -> dict:
+    """What the stability monitor measures along one trajectory (precision_probe.c).
+
+    Every `every` steps: ||M||_F of the FP64 trajectory, |det(M)^2 - 1| of its
+    M by FP64 elimination (the monitor) and by binary128 elimination of the
+    same stored matrix, |det^2 - 1| of M integrated in long double from the
+    same point, and ||M^T J M - J||_F / ||M||_F^2 of the FP64 M."""
+    op = _op(prob)
+    rows = n_steps // every
+    out = np.zeros((rows, 5))
+    rc = _load().orc_monitor_probe(op.ref, _ptr(np.ascontiguousarray(p0, dtype=np.float64)),
+                                   _ptr(np.ascontiguousarray(q0, dtype=np.float64)), int(n_steps), int(every),
+                                   _ptr(out))
+    if rc != 0:
+        raise MemoryError("monitor probe failed to allocate")
+    return {"step": every * np.arange(1, rows + 1), "normM": out[:, 0], "dev_fp64": out[:, 1],
+            "dev_same_M_q": out[:, 2], "dev_longdouble": out[:, 3], "defect": out[:, 4]}
