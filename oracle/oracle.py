@@ -9,7 +9,8 @@ The functions here marshal arguments to the C files, which hold the method's
 arithmetic and cite the paper's equations, with one exception: good_weight,
 the importance-weighted good count of reading R15 (a few lines of numpy,
 documented where it is defined).  precision_probe.c (same library) holds the
-binary128 and long-double checks of what the stability monitor measures.
+binary128 and long-double checks of what the stability monitor measures;
+ta_full.c the double-time form of Eq. (9) without the separable approximation.
 """
 from __future__ import annotations
 
@@ -23,7 +24,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "scivr_oracle.c")
-_SRCS = [_SRC, os.path.join(_HERE, "precision_probe.c")]
+_SRCS = [_SRC, os.path.join(_HERE, "precision_probe.c"), os.path.join(_HERE, "ta_full.c")]
 _LIB = os.environ.get("SCIVR_ORACLE_SO") or os.path.join(_HERE, "libscivr_oracle.so")
 
 # Offsets of the scalar part of the per-trajectory state (after p and q).
@@ -92,6 +93,8 @@ def _load():
         lib.orc_run.argtypes = [P, ctypes.c_int64, d, d, d, d, ctypes.POINTER(ctypes.c_int64), d, d, d,
                                 ctypes.c_int32]
         lib.orc_normalise.argtypes = [P, d, ctypes.c_int64, d]
+        lib.orc_ta_full_run.restype = ctypes.c_int
+        lib.orc_ta_full_run.argtypes = [P, ctypes.c_int64, d, d, d, d, ctypes.POINTER(ctypes.c_int64), d, d]
         lib.orc_monitor_probe.restype = ctypes.c_int
         lib.orc_monitor_probe.argtypes = [P, d, d, ctypes.c_int32, ctypes.c_int32, d]
         _lib = lib
@@ -355,3 +358,39 @@ def monitor_probe(prob, p0, q0, n_steps: int, every: int) -> dict:
         raise MemoryError("monitor probe failed to allocate")
     return {"step": every * np.arange(1, rows + 1), "normM": out[:, 0], "dev_fp64": out[:, 1],
             "dev_same_M_q": out[:, 2], "dev_longdouble": out[:, 3], "defect": out[:, 4]}
+
+
+@dataclass
+class FullResult:
+    spectrum: np.ndarray
+    spec_sum: np.ndarray
+    n_good: int
+    good: np.ndarray
+    lags: Optional[np.ndarray]
+
+
+def run_full(prob, p0, q0, logrho, want_lags: bool = False) -> FullResult:
+    """The double-time estimator of Eq. (9) with each segment's Herman-Kluk
+    prefactor (ta_full.c), normalised as Eq. (11) (good count of reading R15)."""
+    op = _op(prob)
+    F, K, ns = op.F, op.struct.n_energies, op.struct.n_steps
+    p0 = np.ascontiguousarray(p0, dtype=np.float64)
+    q0 = np.ascontiguousarray(q0, dtype=np.float64)
+    logrho = np.ascontiguousarray(logrho, dtype=np.float64)
+    n = int(logrho.shape[0])
+    spec = np.zeros(K)
+    ng = ctypes.c_int64(0)
+    good = np.zeros(n)
+    lags = np.zeros((n, ns + 1, 2)) if want_lags else None
+    rc = _load().orc_ta_full_run(op.ref, n, _ptr(p0), _ptr(q0), _ptr(logrho), _ptr(spec), ctypes.byref(ng),
+                                 _ptr(good), _ptr(lags))
+    if rc != 0:
+        raise MemoryError("full-form oracle failed to allocate")
+    g = good != 0
+    gw = good_weight(prob, p0, q0, logrho, g)
+    I = np.zeros(K)
+    if ng.value > 0:
+        _load().orc_normalise(op.ref, _ptr(spec), ng.value, _ptr(I))
+        I *= ng.value / gw
+    return FullResult(spectrum=I, spec_sum=spec, n_good=int(ng.value), good=g,
+                      lags=None if lags is None else lags[..., 0] + 1j * lags[..., 1])
