@@ -38,6 +38,7 @@
 
 #include "scivr_internal.h"
 #include "traj_common.h"
+#include "group_lu.h"
 
 namespace scivr {
 namespace {
@@ -81,177 +82,12 @@ struct alignas(16) GroupLds : GroupCore<F> {
     char pad[PADN > 0 ? PADN : 32];  // 32 keeps the parity where no padding is needed
 };
 
-// Publishes one element of a pivot row.  The stores stay single 8-byte
-// stores: merged into 16-byte stores they need their two doubles in four
-// consecutive registers, and the register copies that packs them cost more
-// than the extra LDS instructions.
-__device__ inline void publish(double *row, int j, double v)
-{
-    typedef __attribute__((address_space(3))) volatile double lds_vf64;
-    ((lds_vf64 *)row)[j] = v;
-}
-
-// Pivot search of one elimination step: lane `lane` of the group of G lanes
-// publishes its best key, and every lane reads the G keys back (16-byte
-// broadcast reads) and takes their maximum.  The slots are rewritten at the
-// next step; the wave's LDS instructions run in order, so this step's reads
-// complete before any lane's next write.
-template <int G>
-__device__ inline unsigned group_max_key(unsigned *keys, int lane, unsigned mine)
-{
-    lds_order();
-    keys[lane] = mine;
-    lds_order();
-    constexpr int NQ = (G + 3) / 4;
-    unsigned v[4 * NQ];
-#pragma unroll
-    for (int qd = 0; qd < NQ; ++qd) {
-        const uint4 t = reinterpret_cast<const uint4 *>(keys)[qd];
-        v[4 * qd] = t.x;
-        v[4 * qd + 1] = t.y;
-        v[4 * qd + 2] = t.z;
-        v[4 * qd + 3] = t.w;
-    }
-    // a tree of three-input maxima (v_max3_u32)
-    unsigned t[(G + 2) / 3];
-    int nt = 0;
-#pragma unroll
-    for (int i = 0; i < G; i += 3)
-        t[nt++] = (i + 2 < G) ? max(max(v[i], v[i + 1]), v[i + 2]) : (i + 1 < G ? max(v[i], v[i + 1]) : v[i]);
-    unsigned m = t[0];
-    int i = 1;
-#pragma unroll
-    for (; i + 1 < nt; i += 2) m = max(max(m, t[i]), t[i + 1]);
-    if (i < nt) m = max(m, t[i]);
-    return m;
-}
-
-// det of the real N x N matrix (N = 2G) whose rows at positions pos0, pos1
-// live in lane-local a0[], a1[] of lane `lane` of a group of G lanes.  Each
-// step picks the pivot as the largest key (group_max_key) of the live rows'
-// entries in column k; the lane holding the winner publishes that row; live
-// rows read it back and eliminate.  The row at position k and the pivot swap
-// positions, and the determinant changes sign when they differ.  Lookahead:
-// each step updates column k + 1 first and sends the pivot search of step
-// k + 1 off before eliminating the rest of the row, so the search's LDS round
-// trip overlaps that arithmetic (every element sees the same operations in
-// the same order as without it).
-template <int N, int G>
-__device__ inline double lu_det_real2(double (&a0)[N], double (&a1)[N], int pos0, int pos1, int lane, double *piv,
-                                      unsigned *keys)
-{
-    bool alive0 = true, alive1 = true;
-    double det = 1.0;
-    unsigned win;
-    {
-        const unsigned k0 = pivot_key32(fabs(a0[0]), pos0), k1 = pivot_key32(fabs(a1[0]), pos1);
-        win = group_max_key<G>(keys, lane, max(k0, k1));
-    }
-#pragma unroll
-    for (int k = 0; k < N; ++k) {
-        const int ppos = 63 - (int)(win & 63u);
-        const bool isp0 = alive0 && pos0 == ppos;
-        const bool isp1 = alive1 && pos1 == ppos;
-        lds_order();
-        if (isp0) {
-#pragma unroll
-            for (int jj = k; jj < N; ++jj) publish(piv, jj, a0[jj]);
-        }
-        if (isp1) {
-#pragma unroll
-            for (int jj = k; jj < N; ++jj) publish(piv, jj, a1[jj]);
-        }
-        lds_order();
-        const double pk = piv[k];
-        det *= (ppos != k) ? -pk : pk;
-        pos0 = (alive0 && pos0 == k) ? ppos : pos0;
-        pos1 = (alive1 && pos1 == k) ? ppos : pos1;
-        alive0 = alive0 && !isp0;
-        alive1 = alive1 && !isp1;
-        if (k + 1 < N) {
-            // rows already used as pivots are updated too (their keys are
-            // masked, so their values are never read again)
-            const double inv = rcp_nr(pk);
-            const double l0 = a0[k] * inv;
-            const double l1 = a1[k] * inv;
-            const double v = piv[k + 1];
-            a0[k + 1] = fma(-l0, v, a0[k + 1]);
-            a1[k + 1] = fma(-l1, v, a1[k + 1]);
-            const unsigned k0 = alive0 ? pivot_key32(fabs(a0[k + 1]), pos0) : 0u;
-            const unsigned k1 = alive1 ? pivot_key32(fabs(a1[k + 1]), pos1) : 0u;
-            win = group_max_key<G>(keys, lane, max(k0, k1));
-#pragma unroll
-            for (int jj = k + 2; jj < N; ++jj) {
-                const double w = piv[jj];
-                a0[jj] = fma(-l0, w, a0[jj]);
-                a1[jj] = fma(-l1, w, a1[jj]);
-            }
-        }
-    }
-    lds_order();
-    return det;
-}
-
-// det of the complex N x N matrix (N = G) whose row `pos` lives in (ar, ai) of
-// lane `lane`; pivot on |a_k|^2; the pivot row is published interleaved (re,
-// im).  Same pivot search and lookahead as the real elimination.
-template <int N>
-__device__ inline void lu_det_complex(double (&ar)[N], double (&ai)[N], int pos, int lane, double *piv,
-                                      unsigned *keys, double &dr, double &di)
-{
-    bool alive = true;
-    double zr = 1.0, zi = 0.0;
-    unsigned win = group_max_key<N>(keys, lane, pivot_key32(fma(ar[0], ar[0], ai[0] * ai[0]), pos));
-#pragma unroll
-    for (int k = 0; k < N; ++k) {
-        const int ppos = 63 - (int)(win & 63u);
-        const bool isp = alive && pos == ppos;
-        lds_order();
-        if (isp) {
-#pragma unroll
-            for (int jj = k; jj < N; ++jj) {
-                publish(piv, 2 * jj, ar[jj]);
-                publish(piv, 2 * jj + 1, ai[jj]);
-            }
-        }
-        lds_order();
-        const double pr = piv[2 * k], pi = piv[2 * k + 1];
-        const double nr = zr * pr - zi * pi;
-        const double ni = zr * pi + zi * pr;
-        zr = (ppos != k) ? -nr : nr;
-        zi = (ppos != k) ? -ni : ni;
-        pos = (alive && pos == k) ? ppos : pos;
-        alive = alive && !isp;
-        if (k + 1 < N) {
-            const double inv = rcp_nr(fma(pr, pr, pi * pi));
-            const double lr = (ar[k] * pr + ai[k] * pi) * inv;  // a used pivot row is updated too, never read again
-            const double li = (ai[k] * pr - ar[k] * pi) * inv;
-            {
-                const double br = piv[2 * (k + 1)], bi = piv[2 * (k + 1) + 1];
-                ar[k + 1] = fma(-lr, br, fma(li, bi, ar[k + 1]));
-                ai[k + 1] = fma(-lr, bi, fma(-li, br, ai[k + 1]));
-            }
-            const double m2 = fma(ar[k + 1], ar[k + 1], ai[k + 1] * ai[k + 1]);
-            win = group_max_key<N>(keys, lane, alive ? pivot_key32(m2, pos) : 0u);
-#pragma unroll
-            for (int jj = k + 2; jj < N; ++jj) {
-                const double br = piv[2 * jj], bi = piv[2 * jj + 1];
-                ar[jj] = fma(-lr, br, fma(li, bi, ar[jj]));
-                ai[jj] = fma(-lr, bi, fma(-li, br, ai[jj]));
-            }
-        }
-    }
-    lds_order();
-    dr = zr;
-    di = zi;
-}
-
 // The trajectory kernel.  MIXED = false: every trajectory quantity in FP64.
 // MIXED = true: the trajectory (p, q), the potential, gradient and Hessian
 // diagonal and the action (Kahan-compensated) in FP32; the tangent columns,
 // det(A), det(M) and the phase branch stay in FP64; the amplitude, scaled by a
-// per-trajectory power of two 2^e (e ~ -log2 |<chi|z_0>|, 0 <= e <= 12) so that
-// it sits well inside FP16 range, is stored as FP16 hi/lo planes
+// per-trajectory power of two 2^e (e = floor(-log2 |<chi|z_0>|) + 3) so that
+// both FP16 parts of its components stay normal, is stored as FP16 hi/lo planes
 // [re_hi, re_lo, im_hi, im_lo][t / 8][trajectory][t % 8] for the FP16 GEMM.
 template <int F, bool MIXED>
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(traj_waves<F>(), 8)))
@@ -390,8 +226,9 @@ traj_kernel(TrajArgs A, const ProblemDev *__restrict__ P0)
         if constexpr (MIXED) {  // every lane: the ring's lanes store with it
             double ph;
             const double ex0 = overlap(P, ph);
-            // 2^escale ~ 1/|<chi|z_0>|, exact power of two, bounded so |amp| 2^escale < 2^12
-            escale = (int)fmin(fmax(floor(-ex0 * 1.4426950408889634), 0.0), 12.0);
+            // 2^escale: the exact power of two that puts |<chi|z_0>| 2^escale in (4, 8],
+            // so both FP16 parts of every component stay normal (about 22 bits)
+            escale = (int)floor(-ex0 * 1.4426950408889634) + 3;
         }
         if (c == 0 && live) store_amplitude(P, 0);
     }
@@ -504,7 +341,7 @@ traj_kernel(TrajArgs A, const ProblemDev *__restrict__ P0)
                     stash_all[grp][1][i][c] = dpQ[i];
                 }
             }
-            lu_det_complex<F>(are, aim, c, c, L.pivA, L.keys, dAr, dAi);
+            lu_det_complex<F>(are, aim, c, L.pivA, L.keys, dAr, dAi);
         }
 
         // stability monitor |det(M)^2 - 1| on checked steps
@@ -518,7 +355,7 @@ traj_kernel(TrajArgs A, const ProblemDev *__restrict__ P0)
                 r1[i] = STASH ? stash_all[STASH ? grp : 0][1][i][c] : dpQ[i];
                 r1[F + i] = dqQ[i];
             }
-            const double dM = lu_det_real2<N2, F>(r0, r1, c, F + c, c, L.pivM, L.keys);
+            const double dM = lu_det_real2<N2, F>(r0, r1, c, L.pivM, L.keys);
             const double dev = fabs(dM * dM - 1.0);
             detM = dM;
             if (!(dev <= maxdev)) maxdev = dev;

@@ -288,7 +288,7 @@ traj_big_kernel(TrajArgs A, const ProblemDev *__restrict__ P0)
         if constexpr (MIXED) {
             double ph;
             const double ex0 = overlap(P, ph);
-            escale = (int)fmin(fmax(floor(-ex0 * 1.4426950408889634), 0.0), 12.0);
+            escale = (int)floor(-ex0 * 1.4426950408889634) + 3;
         }
         store_amplitude(P, 0);
     }
