@@ -172,12 +172,53 @@ scivr_status scivr_accumulate_spectrum(scivr_ctx *ctx, void *stream);
 scivr_status scivr_accumulate_spectrum_fft(scivr_ctx *ctx, void *stream);
 
 /*
- * Synchronise and write I_k = dt^2/(2 pi T n_good) * total_k to I_host[K]
- * (caller-owned), and the running n_good and n_total.  If n_good is 0 the
- * spectrum is zero-filled and SCIVR_ENOGOOD is returned.  Any output pointer
- * may be NULL.
+ * The same addition to the running totals without the separable
+ * approximation: the double-time form of Eq. (9), in which every segment
+ * [t1, t2] of a trajectory carries the Herman-Kluk prefactor C_{t2}(z(t1)) of
+ * the trajectory started at z(t1) (sqrt(det A) of Eq. (5) from the segment's
+ * own tangent map, on the branch continuous in t2 from C = 1 at t2 = t1).  On
+ * the time samples of Eq. (11), with the diagonal t1 = t2 weighted 1/2,
+ *   total_k += sum_j good_j w_j 2 Re sum_tau R_j(tau) e^{i E_k tau dt},
+ *   R_j(tau) = sum_c omega C_j(c, c + tau) a_j(c + tau) conj(a_j(c)),
+ *   a_j(c) = <chi|z_j(c dt)> e^{i S_j(c dt)},
+ * which equals scivr_accumulate_spectrum's addition when the prefactor is
+ * replaced by exp(i (phi(t2) - phi(t1))).  The trajectories' own stability
+ * flags (from the propagation) select the good ones; segments are not
+ * monitored.  Cost: about n_steps^2 / 2 segment steps per trajectory.  FP64
+ * form and F <= 16 only (else SCIVR_EUNSUPPORTED).  The first call allocates
+ * a lag buffer of about 16 * n_t * max(max_traj, 4096) bytes (SCIVR_ENOMEM if
+ * that fails).  Other errors as scivr_accumulate_spectrum.
+ */
+scivr_status scivr_accumulate_spectrum_full(scivr_ctx *ctx, void *stream);
+
+/*
+ * After scivr_accumulate_spectrum_full: the batch's lag sums R_j(tau) as
+ * complex pairs, R [n][n_steps + 1][2] (caller-owned host memory).
+ * Synchronises.  SCIVR_ESTATE if the batch's last accumulation was another form.
+ */
+scivr_status scivr_read_lags(scivr_ctx *ctx, double *R);
+
+/*
+ * Synchronise and write I_k = dt^2/(2 pi T G) * total_k to I_host[K]
+ * (caller-owned), and the running n_good and n_total.  G is the good count of
+ * Eq. (11) estimated for the sampling density rho of each batch,
+ * G = sum_j good_j H(z_j) / rho(z_j) with H the Husimi density of the
+ * reference state: exactly n_good for Husimi batches, the importance-weighted
+ * count for batches drawn from another density (the learned proposal).  If
+ * n_good is 0 the spectrum is zero-filled and SCIVR_ENOGOOD is returned.  Any
+ * output pointer may be NULL.
  */
 scivr_status scivr_read_spectrum(scivr_ctx *ctx, double *I_host, int64_t *n_good, int64_t *n_total);
+
+/*
+ * Synchronise and write the raw running sums: total[K] = sum over accumulated
+ * batches of sum_j good_j w_j |A_j(E_k)|^2 (or its double-time form), the good
+ * weight G of scivr_read_spectrum, n_good and n_total.  Several contexts (or
+ * shards of one estimate on several devices) combine by adding these and
+ * normalising once as scivr_read_spectrum does.  Any output pointer may be NULL.
+ */
+scivr_status scivr_read_totals(scivr_ctx *ctx, double *total, double *good_weight, int64_t *n_good,
+                               int64_t *n_total);
 
 /* Zero the running spectrum totals and counts (asynchronous on `stream`). */
 scivr_status scivr_reset_spectrum(scivr_ctx *ctx, void *stream);

@@ -23,7 +23,7 @@ LIB = os.path.join(HERE, "libscivr.so")
 ARCH = os.environ.get("SCIVR_OFFLOAD_ARCH", "gfx950")
 
 # largest first: the compile jobs run in parallel
-SOURCES = ["traj_big.hip", "traj.hip", "api.hip", "flow_api.hip", "fourier_fp64.hip", "fourier_f16.hip", "fourier_fft.hip",
+SOURCES = ["traj_big.hip", "traj.hip", "api.hip", "flow_api.hip", "fourier_fp64.hip", "fourier_f16.hip", "fourier_fft.hip", "ta_full.hip",
            "aux_kernels.hip", "flow_kernels.hip"]
 
 HIPCC = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"

@@ -5,6 +5,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <cmath>
 
 #include <new>
@@ -56,7 +57,7 @@ void free_all(scivr_ctx *c)
                     c->d_scal,   c->d_M,         c->d_amp,          c->d_amp16,   c->d_phase, c->d_weight,
                     c->d_part_spec, c->d_part_contrib, c->d_contrib, c->d_total, c->d_ngood, c->d_goodw,
                     c->d_goodw_row, c->d_spart, c->d_fft_part, c->d_fft_S, c->d_fft_pcorr, c->d_fft_corr,
-                    c->d_fft_C};
+                    c->d_fft_C,  c->d_full_part, c->d_full_C};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     for (auto &e : c->events) {
@@ -103,6 +104,60 @@ void fill_math_consts(MathConsts &m)
     m.tan_pio8 = sqrt(2.0) - 1.0;
     m.tan_pio16 = tan(m.pi / 16.0);
     m.tan_3pio16 = tan(3.0 * m.pi / 16.0);
+}
+
+// Scratch of the FFT-autocorrelation accumulation: per-workgroup bins and
+// folded lags, their sums, and the lags C(tau).
+struct FftScratch {
+    double *part, *S;
+    double2 *pcorr, *corr, *C;
+};
+
+scivr_status fft_accumulate_check(scivr_ctx *ctx)
+{
+    if (!ctx->have_initial || ctx->steps_done != ctx->n_steps)
+        return ctx_fail(ctx, SCIVR_ESTATE, "accumulate needs a fully propagated batch (%d of %d steps)", ctx->steps_done,
+                        ctx->n_steps);
+    if (ctx->accumulated) return ctx_fail(ctx, SCIVR_ESTATE, "batch already accumulated");
+    if (fft_log2_length(ctx->nt) > FFT_MAX_LOG2)
+        return ctx_fail(ctx, SCIVR_EUNSUPPORTED, "the FFT accumulation holds at most %d steps (the problem has %d)",
+                        1 << (FFT_MAX_LOG2 - 1), ctx->n_steps);
+    return SCIVR_OK;
+}
+
+// Weights, the FFT form's kernels into the given scratch, and the running
+// totals; `timed` brackets the Fourier step with the context's timing events.
+scivr_status fft_accumulate(scivr_ctx *ctx, hipStream_t s, const FftScratch &b, bool timed)
+{
+    const int L = 1 << fft_log2_length(ctx->nt);
+    HIPCALL(ctx, launch_weights(ctx->d_prob, ctx->F, ctx->d_scal + SC_GOOD * ctx->npad,
+                                ctx->d_scal + SC_ESCALE * ctx->npad, ctx->d_logrho, ctx->d_p0, ctx->d_q0,
+                                ctx->husimi_batch, ctx->n_traj, ctx->npad, ctx->d_weight, ctx->d_goodw_row,
+                                ctx->d_ngood, ctx->d_goodw, s));
+    FftArgs a;
+    a.amp = ctx->d_amp;
+    a.amp16 = ctx->d_amp16;
+    a.plane = (int64_t)ctx->nt16 * ctx->npad;
+    a.weight = ctx->d_weight;
+    a.part = b.part;
+    a.part_corr = b.pcorr;
+    a.n = ctx->n_traj;
+    a.npad = ctx->npad;
+    a.nt = ctx->nt;
+    a.nwg = FFT_NWG;
+    a.fold = (L == 2 * (ctx->nt - 1)) ? 1 : 0;
+    {
+        Timed tm(timed ? ctx : nullptr, s, 2);
+        HIPCALL(ctx, launch_fourier_fft(a, ctx->precision == SCIVR_PRECISION_MIXED, ctx->e_min,
+                                        (ctx->e_max - ctx->e_min) / (double)(ctx->n_energies - 1), ctx->dt,
+                                        ctx->n_energies, b.S, b.corr, b.C, ctx->d_total, s));
+        tm.done();
+    }
+    ctx->n_total += ctx->n_traj;
+    ctx->accumulated = true;
+    ctx->contrib_valid = false;
+    ctx->full_valid = false;
+    return SCIVR_OK;
 }
 
 }  // namespace
@@ -284,6 +339,7 @@ scivr_status scivr_sample_husimi(scivr_ctx *ctx, uint64_t seed, uint64_t first_i
     ctx->have_initial = true;
     ctx->husimi_batch = true;
     ctx->accumulated = false;
+    ctx->full_valid = false;
     return SCIVR_OK;
 }
 
@@ -308,6 +364,7 @@ scivr_status scivr_set_initial(scivr_ctx *ctx, int64_t n_traj, const double *p0,
     ctx->have_initial = true;
     ctx->husimi_batch = false;
     ctx->accumulated = false;
+    ctx->full_valid = false;
     return SCIVR_OK;
 }
 
@@ -343,6 +400,7 @@ scivr_status scivr_propagate(scivr_ctx *ctx, int32_t step_begin, int32_t step_en
     tm.done();
     ctx->steps_done = step_end;
     ctx->accumulated = false;
+    ctx->full_valid = false;
     return SCIVR_OK;
 }
 
@@ -406,69 +464,119 @@ scivr_status scivr_accumulate_spectrum(scivr_ctx *ctx, void *stream)
     ctx->n_total += ctx->n_traj;
     ctx->accumulated = true;
     ctx->contrib_valid = true;
+    ctx->full_valid = false;
     return SCIVR_OK;
 }
 
 scivr_status scivr_accumulate_spectrum_fft(scivr_ctx *ctx, void *stream)
 {
     CHECK_CTX(ctx);
-    if (!ctx->have_initial || ctx->steps_done != ctx->n_steps)
-        return ctx_fail(ctx, SCIVR_ESTATE, "accumulate needs a fully propagated batch (%d of %d steps)", ctx->steps_done,
-                    ctx->n_steps);
-    if (ctx->accumulated) return ctx_fail(ctx, SCIVR_ESTATE, "batch already accumulated");
-    const int lg = fft_log2_length(ctx->nt);
-    if (lg > FFT_MAX_LOG2)
-        return ctx_fail(ctx, SCIVR_EUNSUPPORTED, "the FFT accumulation holds at most %d steps (the problem has %d)",
-                        1 << (FFT_MAX_LOG2 - 1), ctx->n_steps);
-    const int L = 1 << lg;
+    scivr_status st = fft_accumulate_check(ctx);
+    if (st != SCIVR_OK) return st;
     if (!ctx->d_fft_part) {  // scratch for the longest sequence the library takes, on first use
-        const int nwg = 256, Lmax = 1 << FFT_MAX_LOG2;
-        double *part = nullptr, *S = nullptr;
-        double2 *pcorr = nullptr, *corr = nullptr, *C = nullptr;
-        const bool ok = dalloc(&part, (int64_t)nwg * Lmax) == hipSuccess && dalloc(&S, Lmax) == hipSuccess &&
-                        dalloc(&pcorr, nwg) == hipSuccess && dalloc(&corr, 1) == hipSuccess &&
-                        dalloc(&C, Lmax / 2 + 1) == hipSuccess;
+        const int Lmax = 1 << FFT_MAX_LOG2;
+        FftScratch b{};
+        const bool ok = dalloc(&b.part, (int64_t)FFT_NWG * Lmax) == hipSuccess && dalloc(&b.S, Lmax) == hipSuccess &&
+                        dalloc(&b.pcorr, FFT_NWG) == hipSuccess && dalloc(&b.corr, 1) == hipSuccess &&
+                        dalloc(&b.C, Lmax / 2 + 1) == hipSuccess;
         if (!ok) {
-            for (void *q : {(void *)part, (void *)S, (void *)pcorr, (void *)corr, (void *)C})
+            for (void *q : {(void *)b.part, (void *)b.S, (void *)b.pcorr, (void *)b.corr, (void *)b.C})
                 if (q) (void)hipFree(q);
             (void)hipGetLastError();
             return ctx_fail(ctx, SCIVR_ENOMEM, "FFT scratch allocation failed");
         }
-        ctx->fft_nwg = nwg;
-        ctx->d_fft_part = part;
-        ctx->d_fft_S = S;
-        ctx->d_fft_pcorr = pcorr;
-        ctx->d_fft_corr = corr;
-        ctx->d_fft_C = C;
+        ctx->d_fft_part = b.part;
+        ctx->d_fft_S = b.S;
+        ctx->d_fft_pcorr = b.pcorr;
+        ctx->d_fft_corr = b.corr;
+        ctx->d_fft_C = b.C;
+    }
+    const FftScratch b{ctx->d_fft_part, ctx->d_fft_S, ctx->d_fft_pcorr, ctx->d_fft_corr, ctx->d_fft_C};
+    return fft_accumulate(ctx, (hipStream_t)stream, b, true);
+}
+
+scivr_status scivr_accumulate_spectrum_full(scivr_ctx *ctx, void *stream)
+{
+    CHECK_CTX(ctx);
+    if (!ctx->have_initial || ctx->steps_done != ctx->n_steps)
+        return ctx_fail(ctx, SCIVR_ESTATE, "accumulate needs a fully propagated batch (%d of %d steps)", ctx->steps_done,
+                        ctx->n_steps);
+    if (ctx->accumulated) return ctx_fail(ctx, SCIVR_ESTATE, "batch already accumulated");
+    if (ctx->precision != SCIVR_PRECISION_FP64)
+        return ctx_fail(ctx, SCIVR_EUNSUPPORTED, "the double-time form runs in the FP64 form only");
+    if (ctx->F > 16) return ctx_fail(ctx, SCIVR_EUNSUPPORTED, "the double-time form takes F <= 16 (F = %d)", ctx->F);
+    // splits of each trajectory's segment rounds: enough waves to fill the
+    // device, at most one split per round
+    const int W = 64 / ctx->F;
+    const int rounds = ctx->n_steps / W + 1;
+    const int64_t want = (4096 + ctx->max_traj - 1) / ctx->max_traj;
+    const int splits = (int)std::max<int64_t>(1, std::min<int64_t>(want, rounds));
+    if (!ctx->d_full_part) {
+        double2 *part = nullptr, *C = nullptr;
+        const bool ok = dalloc(&part, (int64_t)splits * ctx->nt * ctx->npad) == hipSuccess &&
+                        dalloc(&C, ctx->nt) == hipSuccess;
+        if (!ok) {
+            if (part) (void)hipFree(part);
+            if (C) (void)hipFree(C);
+            (void)hipGetLastError();
+            return ctx_fail(ctx, SCIVR_ENOMEM, "double-time lag buffer allocation failed (%d x %d x %lld)", splits,
+                            ctx->nt, (long long)ctx->npad);
+        }
+        ctx->d_full_part = part;
+        ctx->d_full_C = C;
+        ctx->full_splits = splits;
     }
     hipStream_t s = (hipStream_t)stream;
     HIPCALL(ctx, launch_weights(ctx->d_prob, ctx->F, ctx->d_scal + SC_GOOD * ctx->npad,
                                 ctx->d_scal + SC_ESCALE * ctx->npad, ctx->d_logrho, ctx->d_p0, ctx->d_q0,
                                 ctx->husimi_batch, ctx->n_traj, ctx->npad, ctx->d_weight, ctx->d_goodw_row,
                                 ctx->d_ngood, ctx->d_goodw, s));
-    FftArgs a;
-    a.amp = ctx->d_amp;
-    a.amp16 = ctx->d_amp16;
-    a.plane = (int64_t)ctx->nt16 * ctx->npad;
-    a.weight = ctx->d_weight;
-    a.part = ctx->d_fft_part;
-    a.part_corr = ctx->d_fft_pcorr;
+    FullArgs a;
+    a.prob = ctx->d_prob;
+    a.p0 = ctx->d_p0;
+    a.q0 = ctx->d_q0;
+    a.part = ctx->d_full_part;
     a.n = ctx->n_traj;
     a.npad = ctx->npad;
     a.nt = ctx->nt;
-    a.nwg = ctx->fft_nwg;
-    a.fold = (L == 2 * (ctx->nt - 1)) ? 1 : 0;
+    a.n_steps = ctx->n_steps;
+    a.splits = ctx->full_splits;
+    HIPCALL(ctx, hipMemsetAsync(a.part, 0, sizeof(double2) * (size_t)a.splits * a.nt * a.npad, s));
     {
         Timed tm(ctx, s, 2);
-        HIPCALL(ctx, launch_fourier_fft(a, ctx->precision == SCIVR_PRECISION_MIXED, ctx->e_min,
-                                        (ctx->e_max - ctx->e_min) / (double)(ctx->n_energies - 1), ctx->dt,
-                                        ctx->n_energies, ctx->d_fft_S, ctx->d_fft_corr, ctx->d_fft_C, ctx->d_total,
-                                        s));
+        HIPCALL(ctx, launch_ta_full(ctx->F, a, s));
+        HIPCALL(ctx, launch_ta_lags(a, ctx->d_weight, ctx->d_full_C, s));
+        HIPCALL(ctx, launch_fft_spectrum(ctx->d_full_C, ctx->nt, ctx->n_energies, ctx->e_min,
+                                         (ctx->e_max - ctx->e_min) / (double)(ctx->n_energies - 1), ctx->dt,
+                                         ctx->d_total, s));
         tm.done();
     }
     ctx->n_total += ctx->n_traj;
     ctx->accumulated = true;
     ctx->contrib_valid = false;
+    ctx->full_valid = true;
+    return SCIVR_OK;
+}
+
+scivr_status scivr_read_lags(scivr_ctx *ctx, double *R)
+{
+    CHECK_CTX(ctx);
+    if (!R) return ctx_fail(ctx, SCIVR_EINVAL, "null output");
+    if (!ctx->full_valid) return ctx_fail(ctx, SCIVR_ESTATE, "the last accumulation was not the double-time form");
+    HIPCALL(ctx, hipDeviceSynchronize());
+    const int64_t n = ctx->n_traj, nt = ctx->nt, np = ctx->npad;
+    std::vector<double2> buf((size_t)nt * np);
+    for (int64_t j = 0; j < n; ++j)
+        for (int64_t t = 0; t < nt; ++t) R[(j * nt + t) * 2] = R[(j * nt + t) * 2 + 1] = 0.0;
+    for (int sp = 0; sp < ctx->full_splits; ++sp) {
+        HIPCALL(ctx, hipMemcpy(buf.data(), ctx->d_full_part + (size_t)sp * nt * np, sizeof(double2) * buf.size(),
+                               hipMemcpyDeviceToHost));
+        for (int64_t t = 0; t < nt; ++t)
+            for (int64_t j = 0; j < n; ++j) {
+                R[(j * nt + t) * 2] += buf[(size_t)t * np + j].x;
+                R[(j * nt + t) * 2 + 1] += buf[(size_t)t * np + j].y;
+            }
+    }
     return SCIVR_OK;
 }
 
@@ -493,6 +601,23 @@ scivr_status scivr_read_spectrum(scivr_ctx *ctx, double *I_host, int64_t *n_good
         }
     }
     return ng == 0 ? SCIVR_ENOGOOD : SCIVR_OK;
+}
+
+scivr_status scivr_read_totals(scivr_ctx *ctx, double *total, double *good_weight, int64_t *n_good,
+                               int64_t *n_total)
+{
+    CHECK_CTX(ctx);
+    HIPCALL(ctx, hipDeviceSynchronize());
+    if (total)
+        HIPCALL(ctx, hipMemcpy(total, ctx->d_total, sizeof(double) * ctx->n_energies, hipMemcpyDeviceToHost));
+    if (good_weight) HIPCALL(ctx, hipMemcpy(good_weight, ctx->d_goodw, sizeof(double), hipMemcpyDeviceToHost));
+    if (n_good) {
+        unsigned long long ng = 0;
+        HIPCALL(ctx, hipMemcpy(&ng, ctx->d_ngood, sizeof ng, hipMemcpyDeviceToHost));
+        *n_good = (int64_t)ng;
+    }
+    if (n_total) *n_total = ctx->n_total;
+    return SCIVR_OK;
 }
 
 scivr_status scivr_reset_spectrum(scivr_ctx *ctx, void *stream)

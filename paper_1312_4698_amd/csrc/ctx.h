@@ -43,9 +43,12 @@ struct scivr_ctx {
     bool have_initial = false, accumulated = false;
     bool contrib_valid = false;  // the last accumulation produced per-trajectory contributions (the GEMM does)
     // FFT-autocorrelation accumulation: scratch allocated on first use
-    int32_t fft_nwg = 0;
     double *d_fft_part = nullptr, *d_fft_S = nullptr;
     double2 *d_fft_pcorr = nullptr, *d_fft_corr = nullptr, *d_fft_C = nullptr;
+    // double-time form of Eq. (9): per-split lag sums and the weighted lags, on first use
+    double2 *d_full_part = nullptr, *d_full_C = nullptr;
+    int32_t full_splits = 0;
+    bool full_valid = false;  // the last accumulation was the double-time form (its lags can be read)
     int64_t n_total = 0;     // trajectories accumulated so far
 
     bool device_error = false;
@@ -68,7 +71,7 @@ struct Timed {
     hipEvent_t a = nullptr, b = nullptr;
     Timed(scivr_ctx *c_, hipStream_t s_, int k) : c(c_), s(s_), kind(k)
     {
-        if (c->timing) {
+        if (c && c->timing) {
             if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
                 a = b = nullptr;
                 return;

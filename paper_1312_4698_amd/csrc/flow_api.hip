@@ -605,6 +605,7 @@ scivr_status scivr_flow_sample(scivr_flow *f, uint64_t seed, uint64_t first_inde
     ctx->have_initial = true;
     ctx->husimi_batch = !flow_used;
     ctx->accumulated = false;
+    ctx->full_valid = false;
     return SCIVR_OK;
 }
 

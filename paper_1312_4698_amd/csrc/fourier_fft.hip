@@ -269,6 +269,13 @@ int fft_log2_length(int nt)
     return lg;
 }
 
+hipError_t launch_fft_spectrum(const double2 *C, int nt, int K, double e_min, double de, double dt, double *total,
+                               hipStream_t st)
+{
+    hipLaunchKernelGGL(fft_spectrum_kernel, dim3((K + 127) / 128), dim3(128), 0, st, C, nt, K, e_min, de, dt, total);
+    return hipGetLastError();
+}
+
 hipError_t launch_fourier_fft(const FftArgs &a, bool mixed, double e_min, double de, double dt, int K, double *S,
                               double2 *corr, double2 *C, double *total, hipStream_t st)
 {

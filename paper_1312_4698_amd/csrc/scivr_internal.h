@@ -69,6 +69,7 @@ struct GemmF16Args {
 // FFT-autocorrelation form of the Fourier accumulation: sequences of length
 // L = 2^lg >= 2 (n_t - 1), lg <= FFT_MAX_LOG2 (the whole sequence in LDS).
 constexpr int FFT_MAX_LOG2 = 13;
+constexpr int FFT_NWG = 256;  // workgroups of the per-trajectory transform (one per CU)
 struct FftArgs {
     const double2 *amp;      // FP64 form: [nt_alloc][npad]
     const _Float16 *amp16;   // mixed form: 4 planes [nt16 / 8][npad][8]
@@ -82,6 +83,19 @@ struct FftArgs {
 int fft_log2_length(int nt);
 hipError_t launch_fourier_fft(const FftArgs &a, bool mixed, double e_min, double de, double dt, int K, double *S,
                               double2 *corr, double2 *C, double *total, hipStream_t st);
+
+// Double-time form of Eq. (9) (each segment's own Herman-Kluk prefactor).
+struct FullArgs {
+    const ProblemDev *prob;
+    const double *p0, *q0;  // [F][npad] initial conditions of the batch
+    double2 *part;          // [splits][nt][npad] per-split lag sums R_j(tau)
+    int64_t n, npad;
+    int32_t nt, n_steps, splits;
+};
+hipError_t launch_ta_full(int F, const FullArgs &a, hipStream_t s);
+hipError_t launch_ta_lags(const FullArgs &a, const double *weight, double2 *C, hipStream_t s);
+hipError_t launch_fft_spectrum(const double2 *C, int nt, int K, double e_min, double de, double dt, double *total,
+                               hipStream_t s);
 
 struct GemmArgs {
     const double2 *amp;     // [nt_pad][npad]

@@ -39,7 +39,8 @@ _STATUS = {EINVAL: "SCIVR_EINVAL", ENOMEM: "SCIVR_ENOMEM", EDEVICE: "SCIVR_EDEVI
 EXPORTED = (
     "scivr_abi_version", "scivr_create", "scivr_destroy", "scivr_last_error", "scivr_sample_husimi",
     "scivr_set_initial", "scivr_propagate", "scivr_accumulate_spectrum", "scivr_accumulate_spectrum_fft",
-    "scivr_read_spectrum",
+    "scivr_accumulate_spectrum_full", "scivr_read_lags",
+    "scivr_read_spectrum", "scivr_read_totals",
     "scivr_reset_spectrum", "scivr_batch_info", "scivr_read_initial", "scivr_read_state",
     "scivr_read_amplitudes", "scivr_read_contributions", "scivr_timing_enable", "scivr_kernel_times",
     "scivr_flow_create", "scivr_flow_destroy", "scivr_flow_param_count", "scivr_flow_set_params",
@@ -99,6 +100,9 @@ def load() -> ctypes.CDLL:
         "scivr_propagate": (i32, [v, i32, i32, v]),
         "scivr_accumulate_spectrum": (i32, [v, v]),
         "scivr_accumulate_spectrum_fft": (i32, [v, v]),
+        "scivr_accumulate_spectrum_full": (i32, [v, v]),
+        "scivr_read_lags": (i32, [v, v]),
+        "scivr_read_totals": (i32, [v, v, ctypes.POINTER(d), ctypes.POINTER(i64), ctypes.POINTER(i64)]),
         "scivr_read_spectrum": (i32, [v, v, ctypes.POINTER(i64), ctypes.POINTER(i64)]),
         "scivr_reset_spectrum": (i32, [v, v]),
         "scivr_batch_info": (i32, [v, ctypes.POINTER(i64), ctypes.POINTER(i32)]),
@@ -231,6 +235,17 @@ class Context:
         """The batch's spectrum by the exact FFT-autocorrelation form (``scivr_accumulate_spectrum_fft``)."""
         self._check(self._lib.scivr_accumulate_spectrum_fft(self._h, _stream(stream)))
 
+    def accumulate_full(self, stream=None):
+        """The batch's spectrum by the double-time form of Eq. (9) (``scivr_accumulate_spectrum_full``)."""
+        self._check(self._lib.scivr_accumulate_spectrum_full(self._h, _stream(stream)))
+
+    def read_lags(self):
+        """Lag sums R_j(tau) [n][n_steps + 1] (complex) of the last double-time accumulation."""
+        n, _ = self.batch_info()
+        R = np.zeros((n, self.prob.n_steps + 1, 2))
+        self._check(self._lib.scivr_read_lags(self._h, _np_ptr(R)))
+        return R[..., 0] + 1j * R[..., 1]
+
     def read_spectrum(self):
         """(I [K], n_good, n_total); I is zero when n_good == 0."""
         I = np.zeros(self.prob.n_energies)
@@ -239,6 +254,16 @@ class Context:
         self._check(self._lib.scivr_read_spectrum(self._h, _np_ptr(I), ctypes.byref(ng), ctypes.byref(nt)),
                     allow=(ENOGOOD,))
         return I, int(ng.value), int(nt.value)
+
+    def read_totals(self):
+        """Raw running sums: (total [K], good weight G, n_good, n_total)."""
+        tot = np.zeros(self.prob.n_energies)
+        gw = ctypes.c_double()
+        ng = ctypes.c_int64()
+        nt = ctypes.c_int64()
+        self._check(self._lib.scivr_read_totals(self._h, _np_ptr(tot), ctypes.byref(gw), ctypes.byref(ng),
+                                                ctypes.byref(nt)))
+        return tot, float(gw.value), int(ng.value), int(nt.value)
 
     def reset_spectrum(self, stream=None):
         self._check(self._lib.scivr_reset_spectrum(self._h, _stream(stream)))
@@ -264,12 +289,13 @@ class Context:
         self._check(self._lib.scivr_read_initial(self._h, _np_ptr(p0), _np_ptr(q0), _np_ptr(lr)))
         return p0, q0, lr
 
-    def read_state(self):
+    def read_state(self, want_M: bool = True):
+        """Final state of the batch; without want_M the monodromy matrices are not copied."""
         n, _ = self.batch_info()
         F = self.F
         out = dict(p=np.zeros((F, n)), q=np.zeros((F, n)), S=np.zeros(n), phi=np.zeros(n),
-                   M=np.zeros((n, 2 * F, 2 * F)), good=np.zeros(n, dtype=np.uint8), detM=np.zeros(n),
-                   maxdev=np.zeros(n))
+                   M=np.zeros((n, 2 * F, 2 * F)) if want_M else None, good=np.zeros(n, dtype=np.uint8),
+                   detM=np.zeros(n), maxdev=np.zeros(n))
         self._check(self._lib.scivr_read_state(self._h, *[_np_ptr(out[k]) for k in
                                                           ("p", "q", "S", "phi", "M", "good", "detM", "maxdev")]))
         return out
