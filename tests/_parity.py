@@ -6,7 +6,12 @@ x = (p / sqrt(gamma), sqrt(gamma) q), where a harmonic flow is a rotation;
 i.e. not chaotic enough to amplify rounding differences beyond the tolerance),
 the scaled state (sqrt(gamma) q, p / sqrt(gamma), S, phi) and M~ agree to 1e-9
 relative to max(1, |x|).  Flags agree for every trajectory whose largest |det(M)^2 - 1|
-lies outside the band [5e-7, 2e-6] around the 1e-6 threshold.
+(on either side) lies outside the band [1e-7, 1e-5], a decade either side of
+the 1e-6 threshold: the deviation the monitor measures is FP64 rounding stored
+in M (what the monitor after Eq. (5) catches, shown by the binary128 and long
+double probes), and each side stores its own rounding, so near the threshold
+the two sides' values are independent draws of one noise; over 4096 steps at
+F = 9 they differ by factors up to about 5.
 """
 from __future__ import annotations
 
@@ -14,7 +19,7 @@ import numpy as np
 
 STATE_TOL = 1e-9
 M_NORM_CAP = 1e3
-FLAG_BAND = (5e-7, 2e-6)
+FLAG_BAND = (1e-7, 1e-5)
 
 
 def scaled_monodromy(prob, M):
@@ -58,6 +63,7 @@ def compare_states(prob, gpu: dict, ora, tol: float = STATE_TOL):
     return compared, worst, fails
 
 
-def flags_equal(gpu: dict, ora) -> bool:
+def flag_differences(gpu: dict, ora) -> list:
+    """Indices whose stability flag differs between the two sides."""
     n = gpu["S"].shape[0]
-    return all(bool(gpu["good"][j]) == ora.state(j).good for j in range(n))
+    return [j for j in range(n) if bool(gpu["good"][j]) != ora.state(j).good]

@@ -45,6 +45,31 @@ def _gpu_run(S, prob, seed, n, first_index=0, chunks=None):
     return ctx, I, ng, nt, st, contrib
 
 
+def _rerun_subset(ctx, O, prob, p0, q0, lr, keep):
+    """Re-accumulate the trajectories `keep` on both sides (same points).  If a
+    trajectory's flag now differs (inside the band: points given by the
+    oracle's sampler differ from the device sampler's in the last bits), it
+    is dropped and the subset run again."""
+    keep = np.asarray(keep)
+    for _ in range(4):
+        ctx.reset_spectrum()
+        ctx.set_initial(p0[:, keep], q0[:, keep], lr[keep])
+        ctx.propagate()
+        ctx.accumulate()
+        I, ng, _ = ctx.read_spectrum()
+        contrib = ctx.read_contributions()
+        st = ctx.read_state(want_M=False)
+        ora = O.run(prob, p0[:, keep], q0[:, keep], lr[keep])
+        differ = _parity.flag_differences(st, ora)
+        for j in differ:
+            md = max(ora.state(j).maxdev, st["maxdev"][j])
+            assert _parity.FLAG_BAND[0] <= md <= _parity.FLAG_BAND[1], (keep[j], md)
+        if not differ:
+            return I, ng, contrib, ora
+        keep = np.delete(keep, differ)
+    raise AssertionError("flags kept changing between runs of the same points")
+
+
 CASES = [
     # F, n_traj, n_steps, n_energies, e_max, seed_pot
     (1, 333, 300, 200, 0.05, 1),
@@ -78,13 +103,20 @@ def test_parity_with_oracle(scivr, oracle_mod, F, n, ns, K, emax, sp):
     assert not fails, fails[:5]
     assert compared >= 0.9 * ora.n_good
     assert nt == n
-    if _parity.flags_equal(st, ora):
-        assert ng == ora.n_good
-        scale = np.max(np.abs(ora.spectrum))
-        assert np.max(np.abs(I - ora.spectrum)) <= 1e-9 * scale
-        good = ora.contrib > 0
-        assert np.allclose(contrib[good], ora.contrib[good], rtol=1e-9, atol=1e-9 * ora.contrib.max())
-        assert np.all(contrib[~good] == 0)
+    # flags may differ only inside the band around the threshold (checked
+    # above); such trajectories are dropped on both sides and the batch
+    # re-accumulated, so the spectrum is always compared
+    differ = _parity.flag_differences(st, ora)
+    _say(f"[parity] flags differ (in the band) for {len(differ)} trajectories")
+    if differ:
+        keep = np.setdiff1d(np.arange(n), differ)
+        I, ng, contrib, ora = _rerun_subset(ctx, O, prob, p0o, q0o, lro, keep)
+    assert ng == ora.n_good
+    scale = np.max(np.abs(ora.spectrum))
+    assert np.max(np.abs(I - ora.spectrum)) <= 1e-9 * scale
+    good = ora.contrib > 0
+    assert np.allclose(contrib[good], ora.contrib[good], rtol=1e-9, atol=1e-9 * ora.contrib.max())
+    assert np.all(contrib[~good] == 0)
     # amplitudes of a few trajectories at every time sample
     ora_amp = O.run(prob, p0o[:, :4], q0o[:, :4], lro[:4], want_amps=True).amps
     gpu_amp = ctx.read_amplitudes(0, 4)
@@ -228,6 +260,65 @@ def test_full_size_sampled_parity(scivr, oracle_mod, name):
     ctx.close()
 
 
+@pytest.mark.parametrize("name,n", [("F9_fp64", 2048), ("F6_fp64", 2048)])
+def test_full_shape_spectrum_parity(scivr, oracle_mod, name, n):
+    """The F=9 and F=6 workloads at their full shape (4096 steps, 2048
+    energies) on a contiguous block of 2048 trajectories, every one of them
+    against the oracle.
+      * States: 1e-9 for trajectories good on both sides with a moderate
+        monodromy; flags agree outside the band around the threshold.
+      * Spectrum of the strict block (the trajectories that are either bad on
+        both sides or moderate): 1e-9 of its maximum, n_good exact.
+      * Spectrum of the whole block without the in-band trajectories: the
+        chaotic good ones amplify rounding differences by ||M~||, so it is held
+        to the rounding bound 1e3 u n_steps max ||M~|| and every peak within
+        0.5 cm^-1."""
+    from paper_1312_4698_amd import peaks
+    O = oracle_mod
+    prob, _ = inputs.workload(name)
+    _say(f"[shape] {name} n={n} steps={prob.n_steps} K={prob.n_energies}")
+    p0, q0, lr = O.sample_husimi(prob, 4242, n)
+    ctx = scivr.Context(prob, max_traj=n)
+    ctx.sample_husimi(4242, n, 0)
+    p0g, q0g, lrg = ctx.read_initial()
+    assert np.allclose(p0g, p0, rtol=1e-13, atol=1e-15) and np.allclose(q0g, q0, rtol=1e-13, atol=1e-13)
+    # every run below starts from the oracle's points, bit for bit
+    ctx.set_initial(p0, q0, lr)
+    ctx.propagate()
+    ctx.accumulate()
+    st = ctx.read_state()
+    ora = O.run(prob, p0, q0, lr)
+    compared, worst, fails = _parity.compare_states(prob, st, ora)
+    assert not fails, fails[:5]
+    differ = _parity.flag_differences(st, ora)
+    norms = np.array([np.linalg.norm(_parity.scaled_monodromy(prob, ora.state(j).M)) for j in range(n)])
+    good_o = np.array([ora.state(j).good for j in range(n)])
+    strict = np.array([j for j in range(n) if j not in set(differ) and (not good_o[j] or norms[j] <= _parity.M_NORM_CAP)])
+    agree = np.setdiff1d(np.arange(n), differ)
+    _say(f"[shape] {name}: {compared} states at 1e-9 (worst {worst:.2e}); oracle good {ora.n_good}; "
+         f"flags differ in the band {len(differ)}; strict block {len(strict)}")
+    assert len(strict) >= n // 2
+    I, ng, contrib, oras = _rerun_subset(ctx, O, prob, p0, q0, lr, strict)
+    assert ng == oras.n_good and ng > 0
+    assert np.max(np.abs(I - oras.spectrum)) <= 1e-9 * np.max(oras.spectrum)
+    good = oras.contrib > 0
+    assert np.allclose(contrib[good], oras.contrib[good], rtol=1e-9, atol=1e-9 * oras.contrib.max())
+    I, ng, _, oraa = _rerun_subset(ctx, O, prob, p0, q0, lr, agree)
+    assert ng == oraa.n_good
+    chaotic = [j for j in agree if good_o[j] and norms[j] > _parity.M_NORM_CAP]
+    bound = 1e3 * 2.2e-16 * prob.n_steps * max([1.0] + [norms[j] for j in chaotic])
+    rel = np.max(np.abs(I - oraa.spectrum)) / np.max(oraa.spectrum)
+    E, T = prob.energies(), prob.total_time
+    pr = peaks.find_peaks(E, oraa.spectrum, T)
+    pg = peaks.find_peaks(E, I, T)
+    worst_pk, missing = peaks.peak_errors(pr, pg, tol=20 / inputs.CM1_PER_HARTREE)
+    _say(f"[shape] {name}: whole block rel {rel:.2e} (bound {bound:.1e}, {len(chaotic)} chaotic good); "
+         f"{len(pr)} peaks, worst {worst_pk * inputs.CM1_PER_HARTREE:.4f} cm^-1")
+    assert rel <= bound
+    assert pr and missing == 0 and worst_pk * inputs.CM1_PER_HARTREE <= 0.5
+    ctx.close()
+
+
 def test_full_size_f2_complete_parity(scivr, oracle_mod):
     """The F=2 workload (1024 trajectories, 2048 steps, 512 energies) in full:
     every trajectory and the whole spectrum against the oracle."""
@@ -246,7 +337,7 @@ def test_full_size_f2_complete_parity(scivr, oracle_mod):
     assert compared >= 0.9 * ora.n_good and nt == n
     # trajectories whose monitor sits in the band around the threshold may be
     # flagged differently; the spectrum is compared on both sides without them
-    differ = [j for j in range(n) if bool(st["good"][j]) != ora.state(j).good]
+    differ = _parity.flag_differences(st, ora)
     _say(f"[full] F2 flags differ (in the band) for {len(differ)} trajectories")
     if differ:
         keep = np.setdiff1d(np.arange(n), differ)
