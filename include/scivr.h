@@ -172,6 +172,24 @@ scivr_status scivr_accumulate_spectrum(scivr_ctx *ctx, void *stream);
 scivr_status scivr_accumulate_spectrum_fft(scivr_ctx *ctx, void *stream);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * addition as scivr_accumulate_spectrum_fft, with bit-identical results, that
+ * allocates nothing.  Its scratch is a static device array of
+ * SCIVR_FFT_STATIC_SCRATCH_BYTES (about 16.1 MiB) of which each device the
+ * library runs on holds one copy until the process ends; its device address
+ * is looked up when a context is created on that device.  Every call on one
+ * device shares that copy, and nothing in it needs to start at zero (each
+ * call writes every element it reads), so calls that overlap on one device
+ * (from several host threads or streams) race and give wrong spectra: order
+ * them on one stream.  Limit: at most 4096 steps (L <= 8192), else
+ * SCIVR_EUNSUPPORTED, as the allocating form.  No timing events are recorded.
+ * Other errors as scivr_accumulate_spectrum_fft.
+ */
+#define SCIVR_FFT_STATIC_SCRATCH_BYTES 16912896
+scivr_status scivr_accumulate_spectrum_fft_noalloc(scivr_ctx *ctx, void *stream);
+
+/*
  * The same addition to the running totals without the separable
  * approximation: the double-time form of Eq. (9), in which every segment
  * [t1, t2] of a trajectory carries the Herman-Kluk prefactor C_{t2}(z(t1)) of

@@ -8,6 +8,7 @@
 #include <algorithm>
 #include <cmath>
 
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -112,6 +113,43 @@ struct FftScratch {
     double *part, *S;
     double2 *pcorr, *corr, *C;
 };
+
+// Byte offsets of those buffers in the static scratch (each 256-byte aligned),
+// sized for FFT_NWG workgroups and the longest sequence, L = 2^FFT_MAX_LOG2.
+constexpr size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+constexpr size_t STATIC_LMAX = (size_t)1 << FFT_MAX_LOG2;
+constexpr size_t STATIC_OFF_PART = 0;
+constexpr size_t STATIC_OFF_S = STATIC_OFF_PART + align256(sizeof(double) * FFT_NWG * STATIC_LMAX);
+constexpr size_t STATIC_OFF_PCORR = STATIC_OFF_S + align256(sizeof(double) * STATIC_LMAX);
+constexpr size_t STATIC_OFF_CORR = STATIC_OFF_PCORR + align256(sizeof(double2) * FFT_NWG);
+constexpr size_t STATIC_OFF_C = STATIC_OFF_CORR + align256(sizeof(double2));
+constexpr size_t STATIC_SCRATCH_BYTES = STATIC_OFF_C + align256(sizeof(double2) * (STATIC_LMAX / 2 + 1));
+static_assert(STATIC_SCRATCH_BYTES == SCIVR_FFT_STATIC_SCRATCH_BYTES, "header states the static scratch size");
+
+// The no-allocation FFT accumulation's scratch: one copy per device, held
+// until the process ends, shared by every context on that device.
+static __device__ __align__(256) unsigned char scratch[STATIC_SCRATCH_BYTES];
+
+// Device address of each device's copy of `scratch`, looked up once per
+// device with that device current (at context creation).
+constexpr int STATIC_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[STATIC_MAX_DEVICES] = {};
+
+hipError_t static_scratch_address(int device, void **out)
+{
+    if (device < 0 || device >= STATIC_MAX_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!ptr) return hipErrorInvalidSymbol;
+        g_scratch_ptr[device] = ptr;
+    }
+    *out = g_scratch_ptr[device];
+    return hipSuccess;
+}
 
 scivr_status fft_accumulate_check(scivr_ctx *ctx)
 {
@@ -255,6 +293,11 @@ scivr_status scivr_create(const scivr_problem *p, int32_t device, scivr_ctx **ou
 
     hipError_t e = hipSetDevice(device);
     if (e != hipSuccess) {
+        delete c;
+        return SCIVR_EDEVICE;
+    }
+    if (static_scratch_address(device, &c->d_static_scratch) != hipSuccess) {
+        (void)hipGetLastError();
         delete c;
         return SCIVR_EDEVICE;
     }
@@ -493,6 +536,24 @@ scivr_status scivr_accumulate_spectrum_fft(scivr_ctx *ctx, void *stream)
     }
     const FftScratch b{ctx->d_fft_part, ctx->d_fft_S, ctx->d_fft_pcorr, ctx->d_fft_corr, ctx->d_fft_C};
     return fft_accumulate(ctx, (hipStream_t)stream, b, true);
+}
+
+scivr_status scivr_accumulate_spectrum_fft_noalloc(scivr_ctx *ctx, void *stream)
+{
+    CHECK_CTX(ctx);
+    scivr_status st = fft_accumulate_check(ctx);
+    if (st != SCIVR_OK) return st;
+    // the device address of this device's copy of `scratch`, looked up when
+    // the context was created; the array's name is not a device address here
+    char *base = static_cast<char *>(ctx->d_static_scratch);
+    if (!base) return ctx_fail(ctx, SCIVR_EDEVICE, "no device address for the static FFT scratch");
+    FftScratch b;
+    b.part = reinterpret_cast<double *>(base + STATIC_OFF_PART);
+    b.S = reinterpret_cast<double *>(base + STATIC_OFF_S);
+    b.pcorr = reinterpret_cast<double2 *>(base + STATIC_OFF_PCORR);
+    b.corr = reinterpret_cast<double2 *>(base + STATIC_OFF_CORR);
+    b.C = reinterpret_cast<double2 *>(base + STATIC_OFF_C);
+    return fft_accumulate(ctx, (hipStream_t)stream, b, false);
 }
 
 scivr_status scivr_accumulate_spectrum_full(scivr_ctx *ctx, void *stream)

@@ -42,7 +42,9 @@ struct scivr_ctx {
     int32_t steps_done = 0;
     bool have_initial = false, accumulated = false;
     bool contrib_valid = false;  // the last accumulation produced per-trajectory contributions (the GEMM does)
-    // FFT-autocorrelation accumulation: scratch allocated on first use
+    // FFT-autocorrelation accumulation: scratch allocated on first use, and
+    // the device address of the device's static scratch (no-allocation form)
+    void *d_static_scratch = nullptr;
     double *d_fft_part = nullptr, *d_fft_S = nullptr;
     double2 *d_fft_pcorr = nullptr, *d_fft_corr = nullptr, *d_fft_C = nullptr;
     // double-time form of Eq. (9): per-split lag sums and the weighted lags, on first use

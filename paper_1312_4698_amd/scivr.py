@@ -39,7 +39,7 @@ _STATUS = {EINVAL: "SCIVR_EINVAL", ENOMEM: "SCIVR_ENOMEM", EDEVICE: "SCIVR_EDEVI
 EXPORTED = (
     "scivr_abi_version", "scivr_create", "scivr_destroy", "scivr_last_error", "scivr_sample_husimi",
     "scivr_set_initial", "scivr_propagate", "scivr_accumulate_spectrum", "scivr_accumulate_spectrum_fft",
-    "scivr_accumulate_spectrum_full", "scivr_read_lags",
+    "scivr_accumulate_spectrum_fft_noalloc", "scivr_accumulate_spectrum_full", "scivr_read_lags",
     "scivr_read_spectrum", "scivr_read_totals",
     "scivr_reset_spectrum", "scivr_batch_info", "scivr_read_initial", "scivr_read_state",
     "scivr_read_amplitudes", "scivr_read_contributions", "scivr_timing_enable", "scivr_kernel_times",
@@ -100,6 +100,7 @@ def load() -> ctypes.CDLL:
         "scivr_propagate": (i32, [v, i32, i32, v]),
         "scivr_accumulate_spectrum": (i32, [v, v]),
         "scivr_accumulate_spectrum_fft": (i32, [v, v]),
+        "scivr_accumulate_spectrum_fft_noalloc": (i32, [v, v]),
         "scivr_accumulate_spectrum_full": (i32, [v, v]),
         "scivr_read_lags": (i32, [v, v]),
         "scivr_read_totals": (i32, [v, v, ctypes.POINTER(d), ctypes.POINTER(i64), ctypes.POINTER(i64)]),
@@ -234,6 +235,10 @@ class Context:
     def accumulate_fft(self, stream=None):
         """The batch's spectrum by the exact FFT-autocorrelation form (``scivr_accumulate_spectrum_fft``)."""
         self._check(self._lib.scivr_accumulate_spectrum_fft(self._h, _stream(stream)))
+
+    def accumulate_fft_noalloc(self, stream=None):
+        """The same, with the library's static scratch (``scivr_accumulate_spectrum_fft_noalloc``)."""
+        self._check(self._lib.scivr_accumulate_spectrum_fft_noalloc(self._h, _stream(stream)))
 
     def accumulate_full(self, stream=None):
         """The batch's spectrum by the double-time form of Eq. (9) (``scivr_accumulate_spectrum_full``)."""

@@ -90,6 +90,7 @@ def test_null_arguments_are_rejected():
     assert lib.scivr_propagate(None, 0, 1, None) == S.EINVAL
     assert lib.scivr_accumulate_spectrum(None, None) == S.EINVAL
     assert lib.scivr_accumulate_spectrum_fft(None, None) == S.EINVAL
+    assert lib.scivr_accumulate_spectrum_fft_noalloc(None, None) == S.EINVAL
     assert lib.scivr_read_spectrum(None, None, None, None) == S.EINVAL
     lib.scivr_destroy(None)
     assert lib.scivr_last_error(None) == b"null context"
