@@ -229,6 +229,36 @@ scivr_status scivr_read_lags(scivr_ctx *ctx, double *R);
 scivr_status scivr_read_spectrum(scivr_ctx *ctx, double *I_host, int64_t *n_good, int64_t *n_total);
 
 /*
+ * Several reference states on one trajectory batch (the paper's runs with
+ * different coherent-state combinations, Results and discussion): besides
+ * the problem's chi (reference 0), n_extra more coherent states of the same
+ * widths, centred at p_eq[m][F], q_eq[m][F] (row-major host arrays, read and
+ * copied).  Every later batch then feeds one spectrum per reference state
+ * from the same trajectories: the amplitudes carry <chi_m|z_t>, the weights
+ * w_j = 1/((2 pi)^F rho(z_j)) are shared, and reference m's good count is its
+ * own Husimi mass of the batch, sum_j good_j H_m(z_j) / rho(z_j) (Eq. (11)'s
+ * n_good for points not drawn from H_m).  The Fourier step becomes one product
+ * with a right-hand side per reference state (the phase matrix is shared).
+ * Resets the running totals and discards the current batch.  0 <= n_extra
+ * <= 7 (SCIVR_EINVAL otherwise); FP64 form only (SCIVR_EUNSUPPORTED for the
+ * mixed form; the FFT and double-time accumulations also take one reference
+ * state); SCIVR_ESTATE while a propagated batch awaits accumulation;
+ * SCIVR_ENOMEM if the amplitude buffer for the n_extra + 1 states cannot be
+ * allocated (the context is then unchanged).  Per-trajectory contributions
+ * (scivr_read_contributions) and amplitudes (scivr_read_amplitudes) are
+ * reference 0's.
+ */
+scivr_status scivr_set_references(scivr_ctx *ctx, int32_t n_extra, const double *p_eq, const double *q_eq);
+
+/*
+ * scivr_read_spectrum for reference state `ref` (0 = the problem's chi):
+ * I_k = dt^2/(2 pi T G_ref) total_ref,k with G_ref that state's good count.
+ * SCIVR_EINVAL for a reference outside [0, n_extra].
+ */
+scivr_status scivr_read_spectrum_ref(scivr_ctx *ctx, int32_t ref, double *I_host, int64_t *n_good,
+                                     int64_t *n_total);
+
+/*
  * Synchronise and write the raw running sums: total[K] = sum over accumulated
  * batches of sum_j good_j w_j |A_j(E_k)|^2 (or its double-time form), the good
  * weight G of scivr_read_spectrum, n_good and n_total.  Several contexts (or
@@ -364,12 +394,19 @@ scivr_status scivr_flow_log_density(scivr_flow *flow, int64_t n, const double *p
  * and one uniform from counter (g, 0, 1, 0); if the uniform is below alpha
  * the point is those normals (the Husimi draw), otherwise their image under
  * the flow (BF16 networks on the matrix cores, FP32 affine steps).
- * log_density is ln(alpha N(x) + (1 - alpha) q(x)).  The effective sample size
- * of the ratios N(x_j)/density(x_j), divided by n, goes to *ess_frac; if it
- * is below min_ess_frac the batch is redrawn from the Husimi density with
- * the same seed and indices and *used_flow is 0 (else 1).  alpha = 1 gives
- * exactly scivr_sample_husimi.  Resets the propagation state.  Synchronises.
+ * log_density is ln(alpha N(x) + (1 - alpha) q(x)).  Whether the mixture is
+ * used is decided before the batch is drawn, on a pilot draw of
+ * min(n, SCIVR_FLOW_PILOT_SIZE) mixture points from the disjoint indices
+ * first_index + SCIVR_FLOW_PILOT_OFFSET + j of the same seed: the effective
+ * sample size of their ratios N(x)/density(x), divided by their count, goes
+ * to *ess_frac; if it is below min_ess_frac the batch is drawn from the
+ * Husimi density with the same seed and indices and *used_flow is 0 (else 1).
+ * The choice of estimator therefore does not depend on the batch's own
+ * points, and either estimator is unbiased.  alpha = 1 gives exactly
+ * scivr_sample_husimi.  Resets the propagation state.  Synchronises.
  */
+#define SCIVR_FLOW_PILOT_SIZE 4096
+#define SCIVR_FLOW_PILOT_OFFSET (1ull << 62)
 scivr_status scivr_flow_sample(scivr_flow *flow, uint64_t seed, uint64_t first_index, int64_t n, double alpha,
                                double min_ess_frac, double *ess_frac, int32_t *used_flow, void *stream);
 

@@ -153,6 +153,8 @@ hipError_t static_scratch_address(int device, void **out)
 
 scivr_status fft_accumulate_check(scivr_ctx *ctx)
 {
+    if (ctx->n_refs > 1)
+        return ctx_fail(ctx, SCIVR_EUNSUPPORTED, "the FFT accumulation takes one reference state (%d set)", ctx->n_refs);
     if (!ctx->have_initial || ctx->steps_done != ctx->n_steps)
         return ctx_fail(ctx, SCIVR_ESTATE, "accumulate needs a fully propagated batch (%d of %d steps)", ctx->steps_done,
                         ctx->n_steps);
@@ -266,6 +268,8 @@ scivr_status scivr_create(const scivr_problem *p, int32_t device, scivr_ctx **ou
         h.inv4gamma[i] = 1.0 / (4.0 * p->gamma[i]);
         h.p_eq[i] = p->p_eq[i];
         h.q_eq[i] = p->q_eq[i];
+        h.ref_p[0][i] = p->p_eq[i];
+        h.ref_q[0][i] = p->q_eq[i];
         sg += p->gamma[i];
     }
     for (int i = 0; i < F; ++i)
@@ -290,6 +294,7 @@ scivr_status scivr_create(const scivr_problem *p, int32_t device, scivr_ctx **ou
     h.e_min = p->e_min;
     h.e_max = p->e_max;
     fill_math_consts(h.mc);
+    h.n_refs = 1;
 
     hipError_t e = hipSetDevice(device);
     if (e != hipSuccess) {
@@ -438,6 +443,7 @@ scivr_status scivr_propagate(scivr_ctx *ctx, int32_t step_begin, int32_t step_en
     a.step_end = step_end;
     a.n_steps = ctx->n_steps;
     a.check_every = ctx->check_every;
+    a.n_refs = ctx->n_refs;
     Timed tm(ctx, s, 1);
     HIPCALL(ctx, launch_traj(ctx->F, ctx->precision == SCIVR_PRECISION_MIXED, a, s));
     tm.done();
@@ -459,6 +465,11 @@ scivr_status scivr_accumulate_spectrum(scivr_ctx *ctx, void *stream)
                                 ctx->d_scal + SC_ESCALE * ctx->npad, ctx->d_logrho, ctx->d_p0, ctx->d_q0,
                                 ctx->husimi_batch, ctx->n_traj, ctx->npad, ctx->d_weight, ctx->d_goodw_row,
                                 ctx->d_ngood, ctx->d_goodw, s));
+    // the good count of every further reference state (its Husimi mass of the batch)
+    for (int m = 1; m < ctx->n_refs; ++m)
+        HIPCALL(ctx, launch_ref_good_weights(ctx->d_prob, ctx->F, m, ctx->d_scal + SC_GOOD * ctx->npad, ctx->d_logrho,
+                                             ctx->d_p0, ctx->d_q0, ctx->n_traj, ctx->npad, ctx->d_goodw_row,
+                                             ctx->d_goodw + m, s));
     // only the row tiles that hold trajectories of this batch
     const int32_t row_tiles = (int32_t)((ctx->n_traj + GEMM_BM - 1) / GEMM_BM);
     if (ctx->precision == SCIVR_PRECISION_MIXED) {
@@ -487,10 +498,12 @@ scivr_status scivr_accumulate_spectrum(scivr_ctx *ctx, void *stream)
         g.weight = ctx->d_weight;
         g.part_spec = ctx->d_part_spec;
         g.part_contrib = ctx->d_part_contrib;
-        g.npad = ctx->npad;
+        g.npad = (int64_t)ctx->n_refs * ctx->npad;  // the reference states' row blocks side by side
+        g.ref_rows = ctx->npad;
         g.kpad = ctx->kpad;
         g.nt_pad = ctx->nt_pad;
-        g.row_tiles = row_tiles;
+        g.tiles_per_ref = row_tiles;
+        g.row_tiles = ctx->n_refs * row_tiles;
         g.col_tiles = ctx->col_tiles;
         Timed tm(ctx, s, 2);
         HIPCALL(ctx, launch_fourier_fp64(g, s));
@@ -498,10 +511,13 @@ scivr_status scivr_accumulate_spectrum(scivr_ctx *ctx, void *stream)
     }
     {
         Timed tm(ctx, s, 3);
-        HIPCALL(ctx, launch_spectrum_reduce(ctx->d_part_spec, row_tiles, ctx->n_energies, ctx->kpad, ctx->d_total,
-                                            s));
+        for (int m = 0; m < ctx->n_refs; ++m)
+            HIPCALL(ctx, launch_spectrum_reduce(ctx->d_part_spec + (int64_t)m * row_tiles * ctx->kpad, row_tiles,
+                                                ctx->n_energies, ctx->kpad, ctx->d_total + (int64_t)m * ctx->n_energies,
+                                                s));
+        // per-trajectory contributions of reference state 0
         HIPCALL(ctx, launch_contrib_reduce(ctx->d_part_contrib, ctx->kpad / 64, ctx->d_weight, ctx->n_traj,
-                                           ctx->npad, ctx->d_contrib, s));
+                                           (int64_t)ctx->n_refs * ctx->npad, ctx->d_contrib, s));
         tm.done();
     }
     ctx->n_total += ctx->n_traj;
@@ -566,6 +582,8 @@ scivr_status scivr_accumulate_spectrum_full(scivr_ctx *ctx, void *stream)
     if (ctx->precision != SCIVR_PRECISION_FP64)
         return ctx_fail(ctx, SCIVR_EUNSUPPORTED, "the double-time form runs in the FP64 form only");
     if (ctx->F > 16) return ctx_fail(ctx, SCIVR_EUNSUPPORTED, "the double-time form takes F <= 16 (F = %d)", ctx->F);
+    if (ctx->n_refs > 1)
+        return ctx_fail(ctx, SCIVR_EUNSUPPORTED, "the double-time form takes one reference state (%d set)", ctx->n_refs);
     // splits of each trajectory's segment rounds: enough waves to fill the
     // device, at most one split per round
     const int W = 64 / ctx->F;
@@ -641,27 +659,97 @@ scivr_status scivr_read_lags(scivr_ctx *ctx, double *R)
     return SCIVR_OK;
 }
 
-scivr_status scivr_read_spectrum(scivr_ctx *ctx, double *I_host, int64_t *n_good, int64_t *n_total)
+scivr_status scivr_read_spectrum_ref(scivr_ctx *ctx, int32_t ref, double *I_host, int64_t *n_good,
+                                     int64_t *n_total)
 {
     CHECK_CTX(ctx);
+    if (ref < 0 || ref >= ctx->n_refs)
+        return ctx_fail(ctx, SCIVR_EINVAL, "reference state %d of %d", ref, ctx->n_refs);
     HIPCALL(ctx, hipDeviceSynchronize());
     unsigned long long ng = 0;
     HIPCALL(ctx, hipMemcpy(&ng, ctx->d_ngood, sizeof ng, hipMemcpyDeviceToHost));
     if (n_good) *n_good = (int64_t)ng;
     if (n_total) *n_total = ctx->n_total;
+    double gw = 0.0;
+    HIPCALL(ctx, hipMemcpy(&gw, ctx->d_goodw + ref, sizeof gw, hipMemcpyDeviceToHost));
     if (I_host) {
-        if (ng == 0) {
+        if (ng == 0 || !(gw > 0.0)) {
             for (int k = 0; k < ctx->n_energies; ++k) I_host[k] = 0.0;
         } else {
-            double gw = 0.0;
-            HIPCALL(ctx, hipMemcpy(&gw, ctx->d_goodw, sizeof gw, hipMemcpyDeviceToHost));
-            HIPCALL(ctx, hipMemcpy(I_host, ctx->d_total, sizeof(double) * ctx->n_energies, hipMemcpyDeviceToHost));
+            HIPCALL(ctx, hipMemcpy(I_host, ctx->d_total + (int64_t)ref * ctx->n_energies,
+                                   sizeof(double) * ctx->n_energies, hipMemcpyDeviceToHost));
             const double T = (double)ctx->n_steps * ctx->dt;
             const double scale = ctx->dt * ctx->dt / (2.0 * M_PI * T * gw);
             for (int k = 0; k < ctx->n_energies; ++k) I_host[k] *= scale;
         }
     }
     return ng == 0 ? SCIVR_ENOGOOD : SCIVR_OK;
+}
+
+scivr_status scivr_read_spectrum(scivr_ctx *ctx, double *I_host, int64_t *n_good, int64_t *n_total)
+{
+    return scivr_read_spectrum_ref(ctx, 0, I_host, n_good, n_total);
+}
+
+scivr_status scivr_set_references(scivr_ctx *ctx, int32_t n_extra, const double *p_eq, const double *q_eq)
+{
+    CHECK_CTX(ctx);
+    if (n_extra < 0 || n_extra > MAX_REFS - 1 || (n_extra > 0 && (!p_eq || !q_eq)))
+        return ctx_fail(ctx, SCIVR_EINVAL, "%d further reference states (0 to %d)", n_extra, MAX_REFS - 1);
+    if (n_extra > 0 && ctx->precision != SCIVR_PRECISION_FP64)
+        return ctx_fail(ctx, SCIVR_EUNSUPPORTED, "several reference states run in the FP64 form only");
+    if (ctx->have_initial && !ctx->accumulated)
+        return ctx_fail(ctx, SCIVR_ESTATE, "a batch is in flight (accumulate it first)");
+    const int F = ctx->F;
+    for (int64_t i = 0; i < (int64_t)n_extra * F; ++i)
+        if (!std::isfinite(p_eq[i]) || !std::isfinite(q_eq[i]))
+            return ctx_fail(ctx, SCIVR_EINVAL, "non-finite reference state");
+    const int M = n_extra + 1;
+    // the buffers whose size follows the number of reference states, allocated
+    // before the old ones are released (on failure the context is unchanged)
+    double2 *amp = nullptr;
+    double *part_spec = nullptr, *part_contrib = nullptr, *total = nullptr, *goodw = nullptr;
+    const bool ok = dalloc(&amp, (int64_t)ctx->nt_alloc * M * ctx->npad) == hipSuccess &&
+                    dalloc(&part_spec, (int64_t)M * ctx->row_tiles * ctx->kpad) == hipSuccess &&
+                    dalloc(&part_contrib, (int64_t)(ctx->kpad / 64) * M * ctx->npad) == hipSuccess &&
+                    dalloc(&total, (int64_t)M * ctx->n_energies) == hipSuccess && dalloc(&goodw, M) == hipSuccess;
+    if (!ok) {
+        for (void *q : {(void *)amp, (void *)part_spec, (void *)part_contrib, (void *)total, (void *)goodw})
+            if (q) (void)hipFree(q);
+        (void)hipGetLastError();
+        return ctx_fail(ctx, SCIVR_ENOMEM, "buffers for %d reference states", M);
+    }
+    HIPCALL(ctx, hipDeviceSynchronize());
+    HIPCALL(ctx, launch_fill_zero((double *)amp, 2ll * ctx->nt_alloc * M * ctx->npad, nullptr));
+    for (void *q : {(void *)ctx->d_amp, (void *)ctx->d_part_spec, (void *)ctx->d_part_contrib, (void *)ctx->d_total,
+                    (void *)ctx->d_goodw})
+        if (q) HIPCALL(ctx, hipFree(q));
+    ctx->d_amp = amp;
+    ctx->d_part_spec = part_spec;
+    ctx->d_part_contrib = part_contrib;
+    ctx->d_total = total;
+    ctx->d_goodw = goodw;
+    ctx->n_refs = M;
+    ProblemDev &h = ctx->host_prob;
+    h.n_refs = M;
+    for (int m = 1; m < M; ++m)
+        for (int i = 0; i < F; ++i) {
+            h.ref_p[m][i] = p_eq[(m - 1) * F + i];
+            h.ref_q[m][i] = q_eq[(m - 1) * F + i];
+        }
+    HIPCALL(ctx, hipMemcpy(ctx->d_prob, &h, sizeof h, hipMemcpyHostToDevice));
+    // a fresh estimate: every reference state's totals, n_good and n_total
+    HIPCALL(ctx, launch_fill_zero(ctx->d_total, (int64_t)M * ctx->n_energies, nullptr));
+    HIPCALL(ctx, launch_fill_zero((double *)ctx->d_ngood, 1, nullptr));
+    HIPCALL(ctx, launch_fill_zero(ctx->d_goodw, M, nullptr));
+    HIPCALL(ctx, hipDeviceSynchronize());
+    ctx->n_total = 0;
+    ctx->have_initial = false;
+    ctx->accumulated = false;
+    ctx->contrib_valid = false;
+    ctx->full_valid = false;
+    ctx->steps_done = 0;
+    return SCIVR_OK;
 }
 
 scivr_status scivr_read_totals(scivr_ctx *ctx, double *total, double *good_weight, int64_t *n_good,
@@ -685,9 +773,9 @@ scivr_status scivr_reset_spectrum(scivr_ctx *ctx, void *stream)
 {
     CHECK_CTX(ctx);
     hipStream_t s = (hipStream_t)stream;
-    HIPCALL(ctx, launch_fill_zero(ctx->d_total, ctx->n_energies, s));
+    HIPCALL(ctx, launch_fill_zero(ctx->d_total, (int64_t)ctx->n_refs * ctx->n_energies, s));
     HIPCALL(ctx, launch_fill_zero((double *)ctx->d_ngood, 1, s));
-    HIPCALL(ctx, launch_fill_zero(ctx->d_goodw, 1, s));
+    HIPCALL(ctx, launch_fill_zero(ctx->d_goodw, ctx->n_refs, s));
     ctx->n_total = 0;
     return SCIVR_OK;
 }
@@ -758,8 +846,9 @@ scivr_status scivr_read_amplitudes(scivr_ctx *ctx, int64_t j0, int64_t count, do
     const int nt = ctx->nt;
     if (ctx->precision != SCIVR_PRECISION_MIXED) {
         std::vector<double2> buf((size_t)nt * count);
-        HIPCALL(ctx, hipMemcpy2D(buf.data(), count * sizeof(double2), ctx->d_amp + j0, ctx->npad * sizeof(double2),
-                                 count * sizeof(double2), nt, hipMemcpyDeviceToHost));
+        HIPCALL(ctx, hipMemcpy2D(buf.data(), count * sizeof(double2), ctx->d_amp + j0,
+                                 ctx->n_refs * ctx->npad * sizeof(double2), count * sizeof(double2), nt,
+                                 hipMemcpyDeviceToHost));
         for (int64_t j = 0; j < count; ++j)
             for (int c = 0; c < nt; ++c) {
                 amp[(j * nt + c) * 2] = buf[(size_t)c * count + j].x;

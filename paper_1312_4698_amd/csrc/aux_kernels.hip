@@ -92,6 +92,30 @@ __global__ void weights_kernel(const ProblemDev *__restrict__ P, int F, const do
     if ((threadIdx.x & 63) == 0 && cnt) atomicAdd(n_good, cnt);
 }
 
+// r_j = good_j H_m(z_j) / rho(z_j) for the Husimi density H_m of reference
+// state m (centre ref_p[m], ref_q[m], the problem's widths): each good
+// trajectory's share of reference m's good count (reading of Eq. (11)'s
+// n_good for points not drawn from H_m).
+__global__ void ref_good_weights_kernel(const ProblemDev *__restrict__ P, int F, int m,
+                                        const double *__restrict__ good_row, const double *__restrict__ logrho,
+                                        const double *__restrict__ p0, const double *__restrict__ q0, int64_t n,
+                                        int64_t npad, double *goodw_row)
+{
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= npad) return;
+    double r = 0.0;
+    if (j < n && good_row[j] != 0.0) {
+        double sq = 0.0;
+        for (int i = 0; i < F; ++i) {
+            const double xi = (q0[i * npad + j] - P->ref_q[m][i]) * P->sqrt_gamma[i];
+            const double eta = (p0[i * npad + j] - P->ref_p[m][i]) * P->inv_sqrt_gamma[i];
+            sq += xi * xi + eta * eta;
+        }
+        r = exp(-P->F_log_2pi - 0.5 * sq - logrho[j]);
+    }
+    goodw_row[j] = r;
+}
+
 // total += sum_j row[j] over j < n in a fixed order (one workgroup).
 __global__ void row_sum_kernel(const double *__restrict__ row, int64_t n, double *total)
 {
@@ -164,6 +188,18 @@ hipError_t launch_weights(const ProblemDev *P, int F, const double *good_row, co
 {
     hipLaunchKernelGGL(weights_kernel, dim3(blocks_for(npad, 256)), dim3(256), 0, s, P, F, good_row, escale_row,
                        logrho, p0, q0, husimi ? 1 : 0, n, npad, weight, goodw_row, n_good);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(row_sum_kernel, dim3(1), dim3(256), 0, s, goodw_row, n, goodw_total);
+    return hipGetLastError();
+}
+
+hipError_t launch_ref_good_weights(const ProblemDev *P, int F, int ref, const double *good_row, const double *logrho,
+                                  const double *p0, const double *q0, int64_t n, int64_t npad, double *goodw_row,
+                                  double *goodw_total, hipStream_t s)
+{
+    hipLaunchKernelGGL(ref_good_weights_kernel, dim3(blocks_for(npad, 256)), dim3(256), 0, s, P, F, ref, good_row,
+                       logrho, p0, q0, n, npad, goodw_row);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(row_sum_kernel, dim3(1), dim3(256), 0, s, goodw_row, n, goodw_total);

@@ -8,6 +8,7 @@
 
 #include <cmath>
 #include <new>
+#include <algorithm>
 #include <vector>
 
 #include "ctx.h"
@@ -570,34 +571,47 @@ scivr_status scivr_flow_sample(scivr_flow *f, uint64_t seed, uint64_t first_inde
     hipStream_t s = (hipStream_t)stream;
     const int F = f->sh.F;
     FLOWCALL(f, ensure_inference(f, n));
-    {
-        Timed tm(ctx, s, FLOW_KIND);
-        if (alpha < 1.0) FLOWCALL(f, refresh_bf16(f, s));
-        FLOWCALL(f, launch_flow_draw(seed, first_index, n, F, alpha, f->i_U64, f->i_sel, f->i_Zgen, s));
-        if (alpha < 1.0) FLOWCALL(f, generation_pass(f, f->i_Zgen, n, true, s));
-        FLOWCALL(f, launch_flow_select(ctx->d_prob, F, f->i_U64, f->i_sel, f->i_Zgen, n, ctx->npad, ctx->d_p0,
-                                       ctx->d_q0, f->i_X64, f->i_Z, s));
-        if (alpha < 1.0) FLOWCALL(f, density_pass(f, f->i_Z, n, true, f->i_logq, s));
-        FLOWCALL(f, launch_flow_mixture(f->i_X64, f->i_logq, n, F, ctx->host_prob.F_log_2pi, alpha, ctx->d_logrho,
-                                        f->i_ess, s));
-        tm.done();
-    }
-    const int64_t nblk = (n + 255) / 256;
-    std::vector<double> ep(2 * nblk);
-    FLOWCALL(f, hipMemcpyAsync(ep.data(), f->i_ess, sizeof(double) * 2 * nblk, hipMemcpyDeviceToHost, s));
-    FLOWCALL(f, hipStreamSynchronize(s));
-    double s1 = 0.0, s2 = 0.0;
-    for (int64_t b = 0; b < nblk; ++b) {
-        s1 += ep[2 * b];
-        s2 += ep[2 * b + 1];
-    }
-    const double ess = (s2 > 0.0) ? s1 * s1 / ((double)n * s2) : 0.0;
+    // one draw of m points from the mixture at Philox indices [first, first + m)
+    // into the context's batch, with its effective sample size fraction
+    auto draw = [&](uint64_t first, int64_t m, double *ess) -> scivr_status {
+        {
+            Timed tm(ctx, s, FLOW_KIND);
+            if (alpha < 1.0) FLOWCALL(f, refresh_bf16(f, s));
+            FLOWCALL(f, launch_flow_draw(seed, first, m, F, alpha, f->i_U64, f->i_sel, f->i_Zgen, s));
+            if (alpha < 1.0) FLOWCALL(f, generation_pass(f, f->i_Zgen, m, true, s));
+            FLOWCALL(f, launch_flow_select(ctx->d_prob, F, f->i_U64, f->i_sel, f->i_Zgen, m, ctx->npad, ctx->d_p0,
+                                           ctx->d_q0, f->i_X64, f->i_Z, s));
+            if (alpha < 1.0) FLOWCALL(f, density_pass(f, f->i_Z, m, true, f->i_logq, s));
+            FLOWCALL(f, launch_flow_mixture(f->i_X64, f->i_logq, m, F, ctx->host_prob.F_log_2pi, alpha, ctx->d_logrho,
+                                            f->i_ess, s));
+            tm.done();
+        }
+        const int64_t nblk = (m + 255) / 256;
+        std::vector<double> ep(2 * nblk);
+        FLOWCALL(f, hipMemcpyAsync(ep.data(), f->i_ess, sizeof(double) * 2 * nblk, hipMemcpyDeviceToHost, s));
+        FLOWCALL(f, hipStreamSynchronize(s));
+        double s1 = 0.0, s2 = 0.0;
+        for (int64_t b = 0; b < nblk; ++b) {
+            s1 += ep[2 * b];
+            s2 += ep[2 * b + 1];
+        }
+        *ess = (s2 > 0.0) ? s1 * s1 / ((double)m * s2) : 0.0;
+        return SCIVR_OK;
+    };
+    // the fallback is decided on a pilot draw from indices disjoint from the
+    // batch's, so the choice of estimator does not depend on the batch itself
+    double ess = 0.0;
+    scivr_status st = draw(first_index + SCIVR_FLOW_PILOT_OFFSET, std::min<int64_t>(n, SCIVR_FLOW_PILOT_SIZE), &ess);
+    if (st != SCIVR_OK) return st;
     if (ess_frac) *ess_frac = ess;
-    bool flow_used = true;
-    if (!(ess >= min_ess_frac)) {
+    const bool flow_used = ess >= min_ess_frac;
+    if (flow_used) {
+        double ess_batch = 0.0;
+        st = draw(first_index, n, &ess_batch);
+        if (st != SCIVR_OK) return st;
+    } else {
         FLOWCALL(f, launch_sample_husimi(ctx->d_prob, F, seed, first_index, n, ctx->npad, ctx->d_p0, ctx->d_q0,
                                          ctx->d_logrho, s));
-        flow_used = false;
     }
     if (used_flow) *used_flow = flow_used ? 1 : 0;
     ctx->n_traj = n;

@@ -3,6 +3,11 @@
 //
 //   A_jk = sum_c amp[c][j] * exp(i E_k c dt)          (trajectories x energies)
 //   part_spec[tile][k]    = sum_{j in tile} weight_j |A_jk|^2
+//
+// Several reference states on one batch make it a multi-right-hand-side
+// product: their amplitude matrices stack as row blocks of one left operand
+// (time-major [t][ref][trajectory]) against the one phase matrix, and each
+// row tile's |A|^2 reduction goes to its own reference state's partial sums.
 //   part_contrib[ctile][j] = sum_{k in ctile} |A_jk|^2
 //
 // The complex product is four real v_mfma_f64_16x16x4 per 16x16 block
@@ -40,7 +45,10 @@ __global__ void __launch_bounds__(256, 1) fourier_fp64_kernel(GemmArgs G)
     }
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int wr = wave >> 1, wc = wave & 1;
-    const int64_t row0 = (int64_t)rt * GEMM_BM + wr * 64;
+    // row tile rt is tile rt % tiles_per_ref of reference state rt / tiles_per_ref
+    const int ref = rt / G.tiles_per_ref;
+    const int64_t lrow0 = (int64_t)(rt - ref * G.tiles_per_ref) * GEMM_BM + wr * 64;  // trajectory of the tile's row
+    const int64_t row0 = ref * G.ref_rows + lrow0;
     const int col0 = ct * GEMM_BN + wc * 64;
     const int kk = lane >> 4, ii = lane & 15;
 
@@ -113,7 +121,7 @@ __global__ void __launch_bounds__(256, 1) fourier_fp64_kernel(GemmArgs G)
 #pragma unroll
     for (int bi = 0; bi < 4; ++bi)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) w[bi][r] = G.weight[row0 + bi * 16 + 4 * r + kk];
+        for (int r = 0; r < 4; ++r) w[bi][r] = G.weight[lrow0 + bi * 16 + 4 * r + kk];
 
     __shared__ double lds_spec[2][GEMM_BN];
     double rowsum[4][4];

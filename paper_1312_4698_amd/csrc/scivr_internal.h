@@ -9,6 +9,9 @@
 namespace scivr {
 
 constexpr int FMAX = 32;
+// Reference states whose spectra one batch can feed (the problem's chi and
+// up to MAX_REFS - 1 more of the same widths).
+constexpr int MAX_REFS = 8;
 
 // Tile sizes of the Fourier GEMM: a workgroup covers GEMM_BM trajectories x
 // GEMM_BN energies; the time axis is consumed GEMM_BK samples per MFMA step.
@@ -34,6 +37,8 @@ struct ProblemDev {
     double F_log_2pi;         // F ln(2 pi)
     double e_min, e_max;
     MathConsts mc;            // coefficients of the kernel's exp, sincos, atan2
+    int32_t n_refs;           // reference states of the batch's spectra (1: the problem's chi)
+    double ref_p[MAX_REFS][FMAX], ref_q[MAX_REFS][FMAX];  // their centres; ref 0 = (p_eq, q_eq)
 };
 
 struct TrajArgs {
@@ -44,11 +49,12 @@ struct TrajArgs {
     double *spart;          // [F][npad] per-mode parts of the action, kept between launches
                             // where the small-F kernel splits the action over its lanes
     double *Mst;            // [(2F)^2][npad], element r*2F + c
-    double2 *amp;           // FP64 form: [nt_alloc][npad]
+    double2 *amp;           // FP64 form: [nt_alloc][n_refs][npad]
     _Float16 *amp16;        // mixed form: 4 planes [nt_alloc / 8][npad][8]
     int64_t plane;          // elements per plane of amp16
     int64_t n, npad;
     int32_t step_begin, step_end, n_steps, check_every;
+    int32_t n_refs;         // FP64 form: amplitudes for each reference state
 };
 
 // Time samples per FP16 MFMA k-step of the mixed-form Fourier GEMM.
@@ -98,14 +104,16 @@ hipError_t launch_fft_spectrum(const double2 *C, int nt, int K, double e_min, do
                                hipStream_t s);
 
 struct GemmArgs {
-    const double2 *amp;     // [nt_pad][npad]
+    const double2 *amp;     // [nt_pad][npad]: rows are (reference, trajectory) pairs, ref_rows apart
     const double2 *phase;   // [nt_pad][kpad]
-    const double *weight;   // [npad] good_j * w_j
-    double *part_spec;      // [npad / GEMM_BM][kpad]
+    const double *weight;   // [ref_rows] good_j * w_j, the same for every reference state
+    double *part_spec;      // [row_tiles][kpad]
     double *part_contrib;   // [kpad / 64][npad]
-    int64_t npad;
+    int64_t npad;           // row stride of amp (n_refs x ref_rows)
+    int64_t ref_rows;       // rows of one reference state (the batch capacity)
     int32_t kpad, nt_pad;
     int32_t row_tiles, col_tiles;
+    int32_t tiles_per_ref;  // row tiles holding trajectories, per reference state
 };
 
 hipError_t launch_traj(int F, bool mixed, const TrajArgs &a, hipStream_t s);
@@ -114,6 +122,9 @@ hipError_t launch_sample_husimi(const ProblemDev *P, int F, uint64_t seed, uint6
                                 double *p0, double *q0, double *logrho, hipStream_t s);
 hipError_t launch_phase_table(double e_min, double e_max, int K, int kpad, int nt, int nt_pad, double dt,
                               double2 *phase, hipStream_t s);
+hipError_t launch_ref_good_weights(const ProblemDev *P, int F, int ref, const double *good_row, const double *logrho,
+                                  const double *p0, const double *q0, int64_t n, int64_t npad, double *goodw_row,
+                                  double *goodw_total, hipStream_t s);
 hipError_t launch_weights(const ProblemDev *P, int F, const double *good_row, const double *escale_row,
                           const double *logrho, const double *p0, const double *q0, bool husimi, int64_t n,
                           int64_t npad, double *weight, double *goodw_row, unsigned long long *n_good,

@@ -47,24 +47,28 @@ namespace {
 template <int F>
 constexpr int traj_waves() { return F <= 3 ? 4 : (F <= 6 ? 3 : (F <= 12 ? 2 : 1)); }
 
-template <int F>
+template <int F, bool MULTI>
 struct GroupCore {
     static constexpr int N2 = 2 * F;
     static constexpr int KS = (F + 3) & ~3;
     static constexpr int RB = F < 8 ? F : 8;  // time samples per amplitude ring
     // the overlap's mode terms and the action's parts go through the ring (one
     // per lane) where the kernel runs at most two waves per SIMD; with more
-    // waves the LDS it takes would cost occupancy, and lane 0 sums them itself
+    // waves the LDS it takes would cost occupancy, and lane 0 sums them itself.
+    // With several reference states (MULTI) every lane puts its mode's q and p
+    // into the ring instead, and the lanes that finish a time sample form each
+    // reference state's overlap from them.
     static constexpr bool OVL = traj_waves<F>() <= 2;
-    static constexpr int OT = OVL ? F : 1;
+    static constexpr int OT = (OVL || MULTI) ? F : 1;
+    static constexpr int ST = OVL ? F : 1;
     double pivM[N2];                   // pivot row of the real elimination
     double pivA[N2];                   // pivot row of the complex elimination (re, im interleaved)
     unsigned keys[KS];                 // one pivot key per lane of the group
     // amplitude ring: per time sample, each mode's terms of the exponent and
     // the phase of <chi|p,q>, the action, the det(A) ratio z whose argument
     // advances the prefactor branch, the status flag, and the branch increment
-    double rex[RB][OT], rph[RB][OT];  // without OVL: lane 0's sums, the phase with the action added
-    double rS[RB][OT];                 // with OVL: each lane's part of the action
+    double rex[RB][OT], rph[RB][OT];  // without OVL: lane 0's sums, the phase with the action added; MULTI: q, p
+    double rS[RB][ST];                 // with OVL: each lane's part of the action; MULTI without OVL: lane 0's
     double rzr[RB], rzi[RB], rinc[RB];
     double rtheta, rphi;               // branch and prefactor phase after the last finished sample
     int rflag[RB];
@@ -74,11 +78,11 @@ struct GroupCore {
 // A group's LDS block, padded to an odd multiple of 16 B: the groups of a
 // wave then start 4 * odd banks apart modulo the 64 four-byte banks, so up to
 // 16 groups' simultaneous 16-byte broadcast reads fall into different banks.
-template <int F>
-struct alignas(16) GroupLds : GroupCore<F> {
-    static constexpr int BYTES = (int)((sizeof(GroupCore<F>) + 15) & ~(size_t)15);
+template <int F, bool MULTI>
+struct alignas(16) GroupLds : GroupCore<F, MULTI> {
+    static constexpr int BYTES = (int)((sizeof(GroupCore<F, MULTI>) + 15) & ~(size_t)15);
     static constexpr int PADB = ((BYTES / 16) % 2 == 0) ? 16 : 0;
-    static constexpr int PADN = (BYTES - (int)sizeof(GroupCore<F>)) + PADB;
+    static constexpr int PADN = (BYTES - (int)sizeof(GroupCore<F, MULTI>)) + PADB;
     char pad[PADN > 0 ? PADN : 32];  // 32 keeps the parity where no padding is needed
 };
 
@@ -89,16 +93,19 @@ struct alignas(16) GroupLds : GroupCore<F> {
 // per-trajectory power of two 2^e (e = floor(-log2 |<chi|z_0>|) + 3) so that
 // both FP16 parts of its components stay normal, is stored as FP16 hi/lo planes
 // [re_hi, re_lo, im_hi, im_lo][t / 8][trajectory][t % 8] for the FP16 GEMM.
-template <int F, bool MIXED>
+// MULTI (FP64 only): amplitudes for each of A.n_refs reference states of the
+// problem's widths, [t][ref][trajectory].
+template <int F, bool MIXED, bool MULTI>
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(traj_waves<F>(), 8)))
 traj_kernel(TrajArgs A, const ProblemDev *__restrict__ P0)
 {
+    static_assert(!(MIXED && MULTI), "several reference states run in the FP64 form");
     typedef typename std::conditional<MIXED, float, double>::type R;
     constexpr int N2 = 2 * F;
     constexpr int TPW = 64 / F;
-    __shared__ GroupLds<F> lds_all[TPW];
+    __shared__ GroupLds<F, MULTI> lds_all[TPW];
     __shared__ double lam_lds[F * F];  // coupling matrix, shared by the wave's groups
-    static_assert((sizeof(GroupLds<F>) / 16) % 2 == 1, "group stride must be an odd multiple of 16 B");
+    static_assert((sizeof(GroupLds<F, MULTI>) / 16) % 2 == 1, "group stride must be an odd multiple of 16 B");
     __shared__ R qv_all[TPW][F + (F & 1)], pm_all[TPW][F + (F & 1)];
     __shared__ R ph_all[TPW][F + (F & 1)], pv_all[TPW][F + (F & 1)];
     // The p halves of the lane's two monodromy columns wait in LDS while the
@@ -106,7 +113,8 @@ traj_kernel(TrajArgs A, const ProblemDev *__restrict__ P0)
     // M^T and the pivot traffic at once (F <= 6, three or four waves per SIMD;
     // at two waves per SIMD the LDS round trip costs more than it saves).
     constexpr bool STASH = F <= 6;
-    constexpr bool OVL = GroupCore<F>::OVL;
+    constexpr bool OVL = GroupCore<F, MULTI>::OVL;
+    const int NR = MULTI ? A.n_refs : 1;  // reference states
     __shared__ double stash_all[STASH ? TPW : 1][2][F][F];
 
     const int lane = threadIdx.x;
@@ -118,7 +126,7 @@ traj_kernel(TrajArgs A, const ProblemDev *__restrict__ P0)
     // rest of the wave runs on with them masked off.
     if (grp >= TPW) return;
     const int c = lane - grp * F;  // degree of freedom owned by this lane
-    GroupLds<F> &L = lds_all[grp];
+    GroupLds<F, MULTI> &L = lds_all[grp];
     R *qv = qv_all[grp], *pm = pm_all[grp], *phd = ph_all[grp], *pv = pv_all[grp];
     const int64_t j = (int64_t)blockIdx.x * TPW + grp;
     const bool live = j < A.n;
@@ -194,8 +202,21 @@ traj_kernel(TrajArgs A, const ProblemDev *__restrict__ P0)
         }
         return ex;
     };
+    // exponent and phase of <chi_m|p,q> for reference state m from the modes' q, p
+    auto overlap_ref = [&](auto PP, int m, const double *qs, const double *ps, double &ph) -> double {
+        double ex = 0.0;
+        ph = 0.0;
+#pragma unroll
+        for (int i = 0; i < F; ++i) {
+            const double dqe = PP->ref_q[m][i] - qs[i];
+            const double dpe = PP->ref_p[m][i] - ps[i];
+            ex += -0.25 * PP->gamma[i] * dqe * dqe - dpe * dpe * PP->inv4gamma[i];
+            ph += 0.5 * dqe * (PP->ref_p[m][i] + ps[i]);
+        }
+        return ex;
+    };
     // store the amplitude e^{ex} e^{i phase} of time sample t (zero when bad)
-    auto put_amplitude = [&](auto PP, int t, double ex, double phase, bool g) {
+    auto put_amplitude = [&](auto PP, int t, double ex, double phase, bool g, int m = 0) {
         double s, co;
         dsincos(phase, &PP->mc, &s, &co);
         if constexpr (!MIXED) {
@@ -203,7 +224,7 @@ traj_kernel(TrajArgs A, const ProblemDev *__restrict__ P0)
             double2 r;
             r.x = g ? mag * co : 0.0;
             r.y = g ? mag * s : 0.0;
-            A.amp[(int64_t)t * NP + jr] = r;
+            A.amp[((int64_t)t * NR + m) * NP + jr] = r;
         } else {
             const double mag = ldexp(dexp(ex, &PP->mc), escale);
             const float re = g ? (float)(mag * co) : 0.f, im = g ? (float)(mag * s) : 0.f;
@@ -215,11 +236,25 @@ traj_kernel(TrajArgs A, const ProblemDev *__restrict__ P0)
             for (int pl = 0; pl < 4; ++pl) A.amp16[pl * A.plane + e] = h[pl];
         }
     };
-    // the amplitude <chi|p,q> e^{i(S + phi)} of the published state
+    // the amplitude <chi|p,q> e^{i(S + phi)} of the published state (each reference state's)
     auto store_amplitude = [&](auto PP, int t) {
-        double ph;
-        const double ex = overlap(PP, ph);
-        put_amplitude(PP, t, ex, ph + S.value() + phi, good);
+        if constexpr (MULTI) {
+            double qs[F], ps[F];
+#pragma unroll
+            for (int i = 0; i < F; ++i) {
+                qs[i] = (double)qv[i];
+                ps[i] = (double)pm[i];
+            }
+            for (int m = 0; m < NR; ++m) {
+                double ph;
+                const double ex = overlap_ref(PP, m, qs, ps, ph);
+                put_amplitude(PP, t, ex, ph + S.value() + phi, good, m);
+            }
+        } else {
+            double ph;
+            const double ex = overlap(PP, ph);
+            put_amplitude(PP, t, ex, ph + S.value() + phi, good);
+        }
     };
 
     if (A.step_begin == 0) {
@@ -379,7 +414,7 @@ traj_kernel(TrajArgs A, const ProblemDev *__restrict__ P0)
         // every RB steps (and at the last step of the launch) RB lanes finish
         // one time sample each: the argument, the branch as the running sum of
         // the arguments in time order, phi, the status, exp and sincos.
-        constexpr int RB = GroupCore<F>::RB;
+        constexpr int RB = GroupCore<F, MULTI>::RB;
         const int slot = stp % RB;
         if (c == 0) {
             int ex;
@@ -394,6 +429,9 @@ traj_kernel(TrajArgs A, const ProblemDev *__restrict__ P0)
             prev_i = dAi;
             if constexpr (OVL) {
                 L.rflag[slot] = good ? 1 : 0;  // the finite-action test is on the sum
+            } else if constexpr (MULTI) {
+                L.rflag[slot] = (good && isfinite(S.value())) ? 1 : 0;
+                L.rS[slot][0] = S.value();
             } else {
                 L.rflag[slot] = (good && isfinite(S.value())) ? 1 : 0;
                 double ph;
@@ -401,13 +439,16 @@ traj_kernel(TrajArgs A, const ProblemDev *__restrict__ P0)
                 L.rph[slot][0] = ph + S.value();
             }
         }
-        if constexpr (OVL) {  // mode c's terms of <chi|p,q> and part of the action
+        if constexpr (MULTI) {  // mode c's coordinates
+            L.rex[slot][c] = (double)qc;
+            L.rph[slot][c] = (double)pc;
+        } else if constexpr (OVL) {  // mode c's terms of <chi|p,q>
             const double dqe = Ps->q_eq[c] - (double)qc;
             const double dpe = Ps->p_eq[c] - (double)pc;
             L.rex[slot][c] = -0.25 * Ps->gamma[c] * dqe * dqe - dpe * dpe * Ps->inv4gamma[c];
             L.rph[slot][c] = 0.5 * dqe * (Ps->p_eq[c] + (double)pc);
-            L.rS[slot][c] = S.value();
         }
+        if constexpr (OVL) L.rS[slot][c] = S.value();  // mode c's part of the action
         if (slot == RB - 1 || stp == A.step_end) {
             const int first = max(stp - slot, A.step_begin + 1);  // first time sample in the ring
             const int cnt = stp - first + 1;
@@ -425,20 +466,38 @@ traj_kernel(TrajArgs A, const ProblemDev *__restrict__ P0)
                 // the flag holds the sticky status at that step; a non-finite
                 // branch stays non-finite for every later sample
                 bool g = L.rflag[sl] != 0 && isfinite(ph_);
-                double ex = 0.0, ph = 0.0;
-#pragma unroll
-                for (int i = 0; i < GroupCore<F>::OT; ++i) {
-                    ex += L.rex[sl][i];
-                    ph += L.rph[sl][i];
-                }
-                if constexpr (OVL) {
+                if constexpr (MULTI) {
                     double St = 0.0;
 #pragma unroll
-                    for (int i = 0; i < F; ++i) St += L.rS[sl][i];
-                    g = g && isfinite(St);  // the parts are running sums: once non-finite, always
-                    ph = ph + St;
+                    for (int i = 0; i < GroupCore<F, MULTI>::ST; ++i) St += L.rS[sl][i];
+                    g = g && isfinite(St);
+                    double qs[F], ps[F];
+#pragma unroll
+                    for (int i = 0; i < F; ++i) {
+                        qs[i] = L.rex[sl][i];
+                        ps[i] = L.rph[sl][i];
+                    }
+                    for (int m = 0; m < NR; ++m) {
+                        double ph;
+                        const double ex = overlap_ref(Ps, m, qs, ps, ph);
+                        if (live) put_amplitude(Ps, ts, ex, ph + St + ph_, g, m);
+                    }
+                } else {
+                    double ex = 0.0, ph = 0.0;
+#pragma unroll
+                    for (int i = 0; i < GroupCore<F, MULTI>::OT; ++i) {
+                        ex += L.rex[sl][i];
+                        ph += L.rph[sl][i];
+                    }
+                    if constexpr (OVL) {
+                        double St = 0.0;
+#pragma unroll
+                        for (int i = 0; i < F; ++i) St += L.rS[sl][i];
+                        g = g && isfinite(St);  // the parts are running sums: once non-finite, always
+                        ph = ph + St;
+                    }
+                    if (live) put_amplitude(Ps, ts, ex, ph + ph_, g);
                 }
-                if (live) put_amplitude(Ps, ts, ex, ph + ph_, g);
                 if (c == cnt - 1) {
                     L.rtheta = th;
                     L.rphi = ph_;
@@ -499,7 +558,13 @@ hipError_t launch_F(const TrajArgs &a, hipStream_t s)
     constexpr int TPW = 64 / F;
     const int64_t blocks = (a.n + TPW - 1) / TPW;
     if (blocks <= 0) return hipSuccess;
-    hipLaunchKernelGGL((traj_kernel<F, MIXED>), dim3((unsigned)blocks), dim3(64), 0, s, a, a.prob);
+    if constexpr (!MIXED) {
+        if (a.n_refs > 1) {
+            hipLaunchKernelGGL((traj_kernel<F, false, true>), dim3((unsigned)blocks), dim3(64), 0, s, a, a.prob);
+            return hipGetLastError();
+        }
+    }
+    hipLaunchKernelGGL((traj_kernel<F, MIXED, false>), dim3((unsigned)blocks), dim3(64), 0, s, a, a.prob);
     return hipGetLastError();
 }
 

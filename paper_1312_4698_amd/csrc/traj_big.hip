@@ -262,17 +262,31 @@ traj_big_kernel(TrajArgs A, const ProblemDev *__restrict__ P0)
         return ex;
     };
     auto store_amplitude = [&](auto PP, int t) {
-        double ph;
-        const double ex = overlap(PP, ph);
-        double s, co;
-        dsincos(ph + S.value() + phi, &PP->mc, &s, &co);
         if constexpr (!MIXED) {
-            const double mag = dexp(ex, &PP->mc);
-            double2 r;
-            r.x = good ? mag * co : 0.0;
-            r.y = good ? mag * s : 0.0;
-            A.amp[(int64_t)t * NP + jr] = r;
+            // each reference state's amplitude, [t][ref][trajectory]; ref 0 is chi
+            for (int m = 0; m < A.n_refs; ++m) {
+                double ex = 0.0, ph = 0.0;
+#pragma unroll
+                for (int i = 0; i < F; ++i) {
+                    const double qi = (double)qv[i], pi = (double)pm[i];
+                    const double dqe = PP->ref_q[m][i] - qi;
+                    const double dpe = PP->ref_p[m][i] - pi;
+                    ex += -0.25 * PP->gamma[i] * dqe * dqe - dpe * dpe * PP->inv4gamma[i];
+                    ph += 0.5 * dqe * (PP->ref_p[m][i] + pi);
+                }
+                double s, co;
+                dsincos(ph + S.value() + phi, &PP->mc, &s, &co);
+                const double mag = dexp(ex, &PP->mc);
+                double2 r;
+                r.x = good ? mag * co : 0.0;
+                r.y = good ? mag * s : 0.0;
+                A.amp[((int64_t)t * A.n_refs + m) * NP + jr] = r;
+            }
         } else {
+            double ph;
+            const double ex = overlap(PP, ph);
+            double s, co;
+            dsincos(ph + S.value() + phi, &PP->mc, &s, &co);
             const double mag = ldexp(dexp(ex, &PP->mc), escale);
             const float re = good ? (float)(mag * co) : 0.f, im = good ? (float)(mag * s) : 0.f;
             _Float16 h[4];

@@ -40,7 +40,7 @@ EXPORTED = (
     "scivr_abi_version", "scivr_create", "scivr_destroy", "scivr_last_error", "scivr_sample_husimi",
     "scivr_set_initial", "scivr_propagate", "scivr_accumulate_spectrum", "scivr_accumulate_spectrum_fft",
     "scivr_accumulate_spectrum_fft_noalloc", "scivr_accumulate_spectrum_full", "scivr_read_lags",
-    "scivr_read_spectrum", "scivr_read_totals",
+    "scivr_read_spectrum", "scivr_read_totals", "scivr_set_references", "scivr_read_spectrum_ref",
     "scivr_reset_spectrum", "scivr_batch_info", "scivr_read_initial", "scivr_read_state",
     "scivr_read_amplitudes", "scivr_read_contributions", "scivr_timing_enable", "scivr_kernel_times",
     "scivr_flow_create", "scivr_flow_destroy", "scivr_flow_param_count", "scivr_flow_set_params",
@@ -105,6 +105,8 @@ def load() -> ctypes.CDLL:
         "scivr_read_lags": (i32, [v, v]),
         "scivr_read_totals": (i32, [v, v, ctypes.POINTER(d), ctypes.POINTER(i64), ctypes.POINTER(i64)]),
         "scivr_read_spectrum": (i32, [v, v, ctypes.POINTER(i64), ctypes.POINTER(i64)]),
+        "scivr_read_spectrum_ref": (i32, [v, i32, v, ctypes.POINTER(i64), ctypes.POINTER(i64)]),
+        "scivr_set_references": (i32, [v, i32, v, v]),
         "scivr_reset_spectrum": (i32, [v, v]),
         "scivr_batch_info": (i32, [v, ctypes.POINTER(i64), ctypes.POINTER(i32)]),
         "scivr_read_initial": (i32, [v, v, v, v]),
@@ -251,14 +253,23 @@ class Context:
         self._check(self._lib.scivr_read_lags(self._h, _np_ptr(R)))
         return R[..., 0] + 1j * R[..., 1]
 
-    def read_spectrum(self):
-        """(I [K], n_good, n_total); I is zero when n_good == 0."""
+    def read_spectrum(self, ref: int = 0):
+        """(I [K], n_good, n_total) of reference state `ref` (0: the problem's chi); I is zero when n_good == 0."""
         I = np.zeros(self.prob.n_energies)
         ng = ctypes.c_int64()
         nt = ctypes.c_int64()
-        self._check(self._lib.scivr_read_spectrum(self._h, _np_ptr(I), ctypes.byref(ng), ctypes.byref(nt)),
-                    allow=(ENOGOOD,))
+        if ref == 0:
+            st = self._lib.scivr_read_spectrum(self._h, _np_ptr(I), ctypes.byref(ng), ctypes.byref(nt))
+        else:
+            st = self._lib.scivr_read_spectrum_ref(self._h, int(ref), _np_ptr(I), ctypes.byref(ng), ctypes.byref(nt))
+        self._check(st, allow=(ENOGOOD,))
         return I, int(ng.value), int(nt.value)
+
+    def set_references(self, p_eq, q_eq):
+        """Further reference states [n_extra][F] of the problem's widths, fed by every later batch."""
+        p = np.ascontiguousarray(np.reshape(p_eq, (-1, self.F)), dtype=np.float64)
+        q = np.ascontiguousarray(np.reshape(q_eq, (-1, self.F)), dtype=np.float64)
+        self._check(self._lib.scivr_set_references(self._h, p.shape[0], _np_ptr(p), _np_ptr(q)))
 
     def read_totals(self):
         """Raw running sums: (total [K], good weight G, n_good, n_total)."""

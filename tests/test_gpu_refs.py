@@ -1,0 +1,137 @@
+"""Several reference states on one trajectory batch on the GPU
+(scivr_set_references): each reference state's spectrum against the oracle
+run with that state as chi on the same points, and the harmonic closed form.
+
+The batch is drawn from the Husimi density of the problem's chi; reference m
+reweights the same trajectories (its overlaps <chi_m|z_t>, the shared weights
+and its own good count, sum_j good_j H_m(z_j) / rho(z_j)).  Cases cover the
+three kernel layouts: the small-F ring without per-lane overlap terms (F <= 6),
+with them (F = 9), and one wave per trajectory (F = 17).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1312_4698_amd import inputs
+from tests import _parity
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def scivr():
+    from paper_1312_4698_amd import scivr as S
+    S.load()
+    return S
+
+
+def _refs(prob, k, seed):
+    rng = np.random.default_rng(seed)
+    sg = np.sqrt(prob.gamma)
+    p = rng.uniform(-0.8, 0.8, (k, prob.F)) * sg
+    q = rng.uniform(-0.8, 0.8, (k, prob.F)) / sg
+    return p, q
+
+
+@pytest.mark.parametrize("F,n,ns,K,emax,k", [
+    (2, 300, 300, 200, 0.05, 3),
+    (6, 130, 200, 129, 0.1, 2),
+    (9, 100, 150, 100, 0.1, 7),     # the most reference states
+    (17, 40, 100, 100, 0.15, 2),
+])
+def test_reference_spectra_match_oracle(scivr, oracle_mod, F, n, ns, K, emax, k):
+    O = oracle_mod
+    _say(f"[refs] F={F} n={n} steps={ns} K={K} refs={k + 1}")
+    prob = inputs.morse_quartic(F, F, n_steps=ns, n_energies=K, e_max=emax)
+    pe, qe = _refs(prob, k, 40 + F)
+    ctx = scivr.Context(prob, max_traj=n)
+    ctx.set_references(pe, qe)
+    ctx.sample_husimi(88, n)
+    ctx.propagate()
+    ctx.accumulate()
+    st = ctx.read_state()
+    p0, q0, lr = O.sample_husimi(prob, 88, n)
+    base = O.run(prob, p0, q0, lr)
+    differ = _parity.flag_differences(st, base)
+    assert not differ, differ  # short runs: every flag agrees
+    spectra = [ctx.read_spectrum(m) for m in range(k + 1)]
+    for m in range(k + 1):
+        pm = prob if m == 0 else prob.replace(p_eq=pe[m - 1], q_eq=qe[m - 1])
+        ora = O.run(pm, p0, q0, lr, want_state=False)
+        I, ng, nt = spectra[m]
+        assert ng == ora.n_good and nt == n
+        err = np.max(np.abs(I - ora.spectrum)) / np.max(np.abs(ora.spectrum))
+        _say(f"[refs] ref {m}: max rel diff {err:.2e}")
+        assert err < 1e-9, (m, err)
+    # reference 0 is the plain run's spectrum
+    c0 = scivr.Context(prob, max_traj=n)
+    c0.sample_husimi(88, n)
+    c0.propagate()
+    c0.accumulate()
+    I0, _, _ = c0.read_spectrum()
+    assert np.max(np.abs(spectra[0][0] - I0)) <= 1e-12 * np.max(I0)
+    ctx.close()
+    c0.close()
+
+
+def test_displaced_harmonic_references_from_one_batch(scivr):
+    """Harmonic modes with gamma = omega, batch drawn around the origin: each
+    displaced reference state's spectrum puts the Poisson weights of mean
+    |alpha_i|^2 on the levels; the zero-point line's share is exp(-sum |alpha|^2)."""
+    from tests import _helpers as h
+    om_cm = np.array([2000.0, 3100.0])
+    om = om_cm * inputs.HARTREE_PER_CM1
+    sg = np.sqrt(om)
+    prob = inputs.harmonic(om_cm, n_steps=1024, dt=10.0, e_min=0.0, e_max=0.06, n_energies=300)
+    pe = np.array([sg * [0.8, 0.0], [0.0, 0.0]])
+    qe = np.array([[0.0, 0.0], np.array([0.0, 0.7]) / sg])
+    _say("[refs] harmonic, two displaced references")
+    ctx = scivr.Context(prob, max_traj=8192)
+    ctx.set_references(pe, qe)
+    ctx.run(seed=17, n_traj=8192)
+    E = prob.energies()
+    for m in (1, 2):
+        I, ng, _ = ctx.read_spectrum(m)
+        alpha2 = 0.5 * (prob.gamma * qe[m - 1] ** 2 + pe[m - 1] ** 2 / prob.gamma)
+        ref = np.zeros_like(E)
+        for n0 in range(10):
+            for n1 in range(10):
+                En = om[0] * (n0 + 0.5) + om[1] * (n1 + 0.5)
+                ref += h.poisson(n0, alpha2[0]) * h.poisson(n1, alpha2[1]) * \
+                    h.dirichlet_power(E, [En], prob.dt, prob.n_steps)[:, 0]
+        _say(f"[refs] ref {m}: max |I - Poisson| / max {np.max(np.abs(I - ref)) / ref.max():.3f}")
+        assert np.max(np.abs(I - ref)) < 0.1 * ref.max()
+        k0 = int(np.argmin(np.abs(E - 0.5 * om.sum())))
+        assert abs(I[k0] / ref[k0] - 1) < 0.1
+    ctx.close()
+
+
+def test_reference_state_errors(scivr):
+    _say("[refs] errors")
+    prob = inputs.morse_quartic(2, 2, n_steps=16, n_energies=16)
+    ctx = scivr.Context(prob, max_traj=8)
+    with pytest.raises(scivr.ScivrError, match="EINVAL"):
+        ctx.set_references(np.zeros((8, 2)), np.zeros((8, 2)))  # at most seven more
+    ctx.set_references(np.ones((1, 2)) * 0.01, np.zeros((1, 2)))
+    ctx.sample_husimi(1, 8)
+    ctx.propagate()
+    with pytest.raises(scivr.ScivrError, match="ESTATE"):
+        ctx.set_references(np.zeros((1, 2)), np.zeros((1, 2)))  # batch in flight
+    with pytest.raises(scivr.ScivrError, match="EUNSUPPORTED"):
+        ctx.accumulate_fft()
+    ctx.accumulate()
+    with pytest.raises(scivr.ScivrError, match="EINVAL"):
+        ctx.read_spectrum(2)
+    ctx.set_references(np.zeros((0, 2)), np.zeros((0, 2)))  # back to chi alone
+    ctx.close()
+    pm = prob.replace(precision=inputs.PRECISION_MIXED)
+    cm = scivr.Context(pm, max_traj=8)
+    with pytest.raises(scivr.ScivrError, match="EUNSUPPORTED"):
+        cm.set_references(np.zeros((1, 2)), np.zeros((1, 2)))
+    cm.close()
