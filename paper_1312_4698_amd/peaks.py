@@ -53,3 +53,27 @@ def peak_errors(ref, test, tol: float):
         else:
             worst = max(worst, d)
     return worst, missing
+
+
+def smooth(E: np.ndarray, I: np.ndarray, sigma: float) -> np.ndarray:
+    """I convolved with a normalised Gaussian of standard deviation sigma
+    (hartree) on the uniform grid E, truncated at 4 sigma, edges renormalised:
+    a band of many close levels then has a peak that Monte Carlo ripples at
+    the 2 pi / T scale do not move."""
+    E = np.asarray(E, dtype=np.float64)
+    I = np.asarray(I, dtype=np.float64)
+    de = E[1] - E[0]
+    h = int(math.ceil(4.0 * sigma / de))
+    x = np.arange(-h, h + 1) * de
+    g = np.exp(-0.5 * (x / sigma) ** 2)
+    num = np.convolve(I, g, mode="same")
+    den = np.convolve(np.ones_like(I), g, mode="same")
+    return num / den
+
+
+def centroid(E: np.ndarray, I: np.ndarray, lo: float, hi: float) -> float:
+    """First moment of I over the window [lo, hi] (hartree)."""
+    E = np.asarray(E, dtype=np.float64)
+    I = np.asarray(I, dtype=np.float64)
+    m = (E >= lo) & (E <= hi)
+    return float(np.sum(E[m] * I[m]) / np.sum(I[m]))
