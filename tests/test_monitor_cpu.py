@@ -60,3 +60,44 @@ def test_monitor_measures_integration_rounding_f30(oracle_mod):
     k = _check_crossing(r, prob.det_tol)
     assert r["step"][k] <= 2048
     assert abs(np.log(r["dev_same_M_q"][k] / r["dev_fp64"][k])) < 1.0
+
+
+def test_single_precision_monodromy_cannot_be_monitored_at_1e6(oracle_mod):
+    """Why the mixed form keeps the monodromy matrix M in FP64 (and does not
+    take the F = 30 kick products on FP32 matrix cores): the tangent map of
+    an F = 30 trajectory of the workload, propagated through the same
+    drift-kick stages with the oracle's Hessians, keeps |det(M)^2 - 1| near
+    1e-13 in FP64 but passes the paper's 1e-6 within the first 64 steps in
+    FP32 and grows past 1e-5 by step 256 of 8192: the sticky monitor would
+    drop every trajectory at once."""
+    O = oracle_mod
+    prob, _ = inputs.workload("F30_fp64")
+    F = prob.F
+    d, c = O.yoshida_coefficients()
+    op = O.OracleProblem(prob)
+    p0, q0, _ = O.sample_husimi(prob, 2024, 2)
+    for j in range(2):
+        p, q = p0[:, j].copy(), q0[:, j].copy()
+        M64, M32 = np.eye(2 * F), np.eye(2 * F, dtype=np.float32)
+        first = None
+        for step in range(1, 257):
+            for s_ in range(4):
+                h = d[s_] * prob.dt
+                q = q + h * p
+                M64[F:] += h * M64[:F]
+                M32[F:] += np.float32(h) * M32[:F]
+                if s_ == 3:
+                    break
+                _, g, H = O.potential(op, q)
+                hk = c[s_] * prob.dt
+                p = p - hk * g
+                M64[:F] -= hk * (H @ M64[F:])
+                M32[:F] -= np.float32(hk) * (H.astype(np.float32) @ M32[F:])
+            if step % 32 == 0:
+                d64 = abs(np.linalg.det(M64) ** 2 - 1.0)
+                d32 = abs(np.linalg.det(M32.astype(np.float64)) ** 2 - 1.0)
+                assert d64 < 1e-11, (j, step, d64)
+                if first is None and d32 > prob.det_tol:
+                    first = step
+        assert first is not None and first <= 64, (j, first)
+        assert d32 > 1e-5, (j, d32)
