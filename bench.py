@@ -81,18 +81,89 @@ def _profile_traffic(kernel_prefix: str, src_hash: str):
     return float(b.group(1))
 
 
-def cpu_baseline(prob, n_sample: int, seed: int):
-    """The oracle as it stands, on all host cores, over a bounded sample."""
+def _cpu_model() -> str:
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(prob, n_sample: int, seed: int, n_single: int = 0):
+    """The oracle as it stands, on all host cores, over a bounded sample; and,
+    if n_single > 0, on one thread over the first n_single of those points (the
+    paper times its CPU code on a single thread)."""
     from oracle import oracle as O
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     p0, q0, lr = O.sample_husimi(prob, seed, n_sample)
     t0 = time.perf_counter()
     O.run(prob, p0, q0, lr, want_state=False, want_contrib=False, n_threads=threads)
     dt = time.perf_counter() - t0
-    return {"value": n_sample * prob.n_steps / dt, "unit": "trajectory-steps/s", "cores": threads,
-            "kind": "oracle",
-            "sample": f"{n_sample} trajectories of the same workload (all {prob.n_steps} steps, "
-                      f"{prob.n_energies} energies), {dt:.1f} s wall"}
+    out = {"value": n_sample * prob.n_steps / dt, "unit": "trajectory-steps/s", "cores": threads,
+           "kind": "oracle", "cpu_model": _cpu_model(),
+           "sample": f"{n_sample} trajectories of the same workload (all {prob.n_steps} steps, "
+                     f"{prob.n_energies} energies), {dt:.1f} s wall"}
+    if n_single > 0:
+        t0 = time.perf_counter()
+        O.run(prob, p0[:, :n_single], q0[:, :n_single], lr[:n_single], want_state=False, want_contrib=False,
+              n_threads=1)
+        d1 = time.perf_counter() - t0
+        out["single_thread"] = {"value": n_single * prob.n_steps / d1, "unit": "trajectory-steps/s", "cores": 1,
+                                "sample": f"the first {n_single} of those trajectories, {d1:.1f} s wall"}
+    return out
+
+
+def oracle_full(name: str, chunk: int = 2048):
+    """The oracle over a whole workload on all host cores, in chunks of
+    trajectories with a progress line each; its rate and the host."""
+    from oracle import oracle as O
+    from paper_1312_4698_amd import inputs
+    prob, n = inputs.workload(name)
+    prob = prob.replace(precision=inputs.PRECISION_FP64)
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    total = 0.0
+    for j0 in range(0, n, chunk):
+        m = min(chunk, n - j0)
+        p0, q0, lr = O.sample_husimi(prob, 77, m, first_index=j0)
+        t0 = time.perf_counter()
+        O.run(prob, p0, q0, lr, want_state=False, want_contrib=False, n_threads=threads)
+        total += time.perf_counter() - t0
+        print(f"[oracle] {name}: {j0 + m} of {n} trajectories, {total:.1f} s", file=sys.stderr, flush=True)
+    return {"workload": name, "n_traj": n, "n_steps": prob.n_steps, "n_energies": prob.n_energies, "seconds": total,
+            "trajectory_steps_per_s": n * prob.n_steps / total, "cores": threads, "cpu_model": _cpu_model()}
+
+
+def x1_sweep(scivr, torch, inputs, name: str, log2_sizes, reps: int = 3):
+    """Throughput of one form against the trajectory count (one batch of N
+    trajectories per step, sample + propagate + accumulate), median of `reps`
+    timed steps after one warm-up step per size; one JSON line per size on
+    stdout and the knee (the smallest N within 10 % of the largest rate)."""
+    prob, _ = inputs.workload(name)
+    stream = torch.cuda.current_stream()
+    rows = []
+    for lg in log2_sizes:
+        n = 1 << lg
+        ctx = scivr.Context(prob, max_traj=n)
+        times = []
+        for i in range(reps + 1):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ctx.sample_husimi(seed=500 + i, n_traj=n, stream=stream)
+            ctx.propagate(0, prob.n_steps, stream=stream)
+            ctx.accumulate(stream=stream)
+            torch.cuda.synchronize()
+            if i > 0:
+                times.append(time.perf_counter() - t0)
+        ctx.close()
+        t = float(np.median(times))
+        row = {"sweep": name, "n_traj": n, "s_per_step": t, "trajectory_steps_per_s": n * prob.n_steps / t}
+        rows.append(row)
+        print(json.dumps(row), flush=True)
+    best = max(r["trajectory_steps_per_s"] for r in rows)
+    knee = next(r["n_traj"] for r in rows if r["trajectory_steps_per_s"] >= 0.9 * best)
+    return {"workload": name, "rows": rows, "knee_n_traj": knee, "best_trajectory_steps_per_s": best}
 
 
 def _energy_reader():
@@ -184,26 +255,71 @@ def _peak_error_cm(peaks, inputs, E, T, ref_peaks, I):
     return float("inf") if missing else worst * inputs.CM1_PER_HARTREE
 
 
-def learned_study(scivr, inputs, peaks, prob, ref_I, sizes, seeds, n_train, layers, width, epochs, batch, lr,
-                  alpha):
-    """Trajectories needed for a 1 cm^-1 peak error against the reference spectrum,
-    plain Husimi sampling vs the learned proposal, in the given form of `prob`.
+def _half_max_centre(E, I, e0, tol):
+    """Midpoint of the half-maximum crossings of the peak nearest e0 (linear
+    interpolation between grid points): a position that stays defined on a
+    broad, flat-topped peak."""
+    k0 = int(np.argmin(np.abs(E - e0)))
+    lo, hi = max(k0 - int(tol / (E[1] - E[0])), 1), min(k0 + int(tol / (E[1] - E[0])), E.size - 2)
+    k = lo + int(np.argmax(I[lo:hi + 1]))
+    half = 0.5 * I[k]
+    a = k
+    while a > 0 and I[a] > half:
+        a -= 1
+    b = k
+    while b < E.size - 1 and I[b] > half:
+        b += 1
+    if I[a] > half or I[b] > half:
+        return None
+    ea = E[a] + (half - I[a]) / (I[a + 1] - I[a]) * (E[1] - E[0])
+    eb = E[b - 1] + (I[b - 1] - half) / (I[b - 1] - I[b]) * (E[1] - E[0])
+    return 0.5 * (ea + eb)
 
-    For each seed and each N in `sizes` an independent batch of N trajectories
-    (Philox indices disjoint from the reference run's) gives a spectrum; its largest
-    peak shift against the reference is recorded; N_to_1cm is the smallest N whose
-    median shift over the seeds is <= 1 cm^-1.  The flow is trained once on the
-    contributions of a Husimi batch of n_train trajectories.
-    """
-    E, T = prob.energies(), prob.total_time
-    jp = peaks.find_peaks(E, ref_I, T)
+
+def learned_study(scivr, inputs, peaks, prob, ref_I, sizes, seeds, n_train, layers, width, epochs, batch, lr,
+                  alpha, judge_batches=4, window=0.01, n_fine=2048, n_boot=2000):
+    """The learned proposal against plain Husimi sampling, in the form of `prob`.
+
+    The comparison runs on a fine energy grid (n_fine points over +-window
+    hartree around the main peak of the timed run's spectrum `ref_I`), where
+    a plain FP64 judge of judge_batches x max(sizes) Husimi trajectories gives
+    the reference spectrum and peak.  For each of the seeds and each N in
+    `sizes`, an independent batch of N trajectories (Philox indices disjoint
+    from the judge's) gives a spectrum, its peak position error (R13 vertex,
+    and the half-maximum midpoint), and its relative RMS error.  Reported:
+      * the variance ratio plain / learned at equal N (median over N of the
+        squared RMS ratio), the robust figure;
+      * per N, the median peak error over the seeds with a bootstrap 16-84 %
+        interval (resampling seeds);
+      * N_to_1cm: the smallest N from which on the median stays <= 1 cm^-1,
+        and N_to_1cm_fit: where a * N^-1/2, fitted to the medians, crosses 1.
+    The flow is trained once on the contributions of a Husimi batch of n_train
+    trajectories on the fine grid."""
+    CM = inputs.CM1_PER_HARTREE
+    E0, T = prob.energies(), prob.total_time
+    e_peak = peaks.find_peaks(E0, ref_I, T)
+    e_main = max(e_peak, key=lambda p: p[1])[0]
+    fine = prob.replace(e_min=e_main - window, e_max=e_main + window, n_energies=n_fine)
+    E = fine.energies()
+    tol = 20.0 / CM
     cap = max(max(sizes), n_train)
-    ctx = scivr.Context(prob, max_traj=cap)
-    base = 1 << 40  # Philox indices far from the reference run's
+    # the judge: plain FP64 on the fine grid
+    jprob = fine.replace(precision=inputs.PRECISION_FP64)
+    jctx = scivr.Context(jprob, max_traj=max(sizes))
+    for b in range(judge_batches):
+        jctx.run(seed=9001, n_traj=max(sizes), first_index=b * max(sizes))
+    judge, _, _ = jctx.read_spectrum()
+    jctx.close()
+    jp = [p for p in peaks.find_peaks(E, judge, T) if abs(p[0] - e_main) < tol]
+    e_ref = jp[0][0] if jp else e_main
+    h_ref = _half_max_centre(E, judge, e_ref, tol)
+    ctx = scivr.Context(fine, max_traj=cap)
+    base = 1 << 40  # Philox indices far from the judge's
 
     def sweep(draw):
-        errs = np.zeros((len(seeds), len(sizes)))
-        rms = np.zeros_like(errs)
+        vert = np.full((len(seeds), len(sizes)), np.inf)
+        half = np.full_like(vert, np.inf)
+        rms = np.zeros_like(vert)
         for a, sd in enumerate(seeds):
             for b, N in enumerate(sizes):
                 ctx.reset_spectrum()
@@ -211,22 +327,35 @@ def learned_study(scivr, inputs, peaks, prob, ref_I, sizes, seeds, n_train, laye
                 ctx.propagate()
                 ctx.accumulate()
                 I, _, _ = ctx.read_spectrum()
-                errs[a, b] = _peak_error_cm(peaks, inputs, E, T, jp, I)
-                rms[a, b] = float(np.sqrt(np.mean((I - ref_I) ** 2)) / ref_I.max())
-        med = np.median(errs, axis=0)
-        # smallest N from which on every larger N of the sweep also meets 1 cm^-1
+                pk = [p for p in peaks.find_peaks(E, I, T) if abs(p[0] - e_ref) < tol]
+                if pk:
+                    vert[a, b] = abs(min(pk, key=lambda p: abs(p[0] - e_ref))[0] - e_ref) * CM
+                hc = _half_max_centre(E, I, e_ref, tol)
+                if hc is not None and h_ref is not None:
+                    half[a, b] = abs(hc - h_ref) * CM
+                rms[a, b] = float(np.sqrt(np.mean((I - judge) ** 2)) / judge.max())
+        rng = np.random.default_rng(12345)
+        boots = np.array([np.median(vert[rng.integers(0, len(seeds), len(seeds))], axis=0) for _ in range(n_boot)])
+        med = np.median(vert, axis=0)
         n1 = None
         for b in range(len(sizes) - 1, -1, -1):
             if med[b] <= 1.0:
                 n1 = sizes[b]
             else:
                 break
-        return {"N_to_1cm": n1, "median_peak_error_cm1": med.tolist(),
+        fin = np.isfinite(med) & (med > 0)
+        a_fit = float(np.exp(np.mean(np.log(med[fin] * np.sqrt(np.array(sizes)[fin]))))) if fin.any() else None
+        return {"N_to_1cm": n1, "N_to_1cm_fit": None if a_fit is None else a_fit ** 2,
+                "median_peak_error_cm1": med.tolist(),
+                "peak_error_cm1_16_84": [np.percentile(boots, 16, axis=0).tolist(),
+                                         np.percentile(boots, 84, axis=0).tolist()],
+                "median_half_max_error_cm1": np.median(half, axis=0).tolist(),
                 "median_rel_rms": np.median(rms, axis=0).tolist()}
 
     t0 = time.perf_counter()
     plain = sweep(lambda sd, N: ctx.sample_husimi(seed=sd, n_traj=N, first_index=base))
     t_plain = time.perf_counter() - t0
+    print("[bench] learned-proposal study: plain sweep done", file=sys.stderr, flush=True)
     flow = scivr.Flow(ctx, layers, width, seed=5)
     ctx.reset_spectrum()
     ctx.run(seed=4242, n_traj=n_train, first_index=2 * base)
@@ -248,7 +377,14 @@ def learned_study(scivr, inputs, peaks, prob, ref_I, sizes, seeds, n_train, laye
     ratio = np.array(plain["median_rel_rms"]) / np.array(learned["median_rel_rms"])
     return {
         "variance_ratio_plain_over_learned": float(np.median(ratio ** 2)),
-        "sizes": list(sizes), "seeds": list(seeds), "ref_peaks_cm1": [e * inputs.CM1_PER_HARTREE for e, _ in jp],
+        "variance_ratio_per_N": (ratio ** 2).tolist(),
+        "N_ratio_fit_plain_over_learned": (None if not (plain["N_to_1cm_fit"] and learned["N_to_1cm_fit"]) else
+                                           plain["N_to_1cm_fit"] / learned["N_to_1cm_fit"]),
+        "sizes": list(sizes), "seeds": len(seeds), "fine_grid": {"e_min": fine.e_min, "e_max": fine.e_max,
+                                                                 "n_energies": n_fine,
+                                                                 "spacing_cm1": (E[1] - E[0]) * CM},
+        "judge": {"trajectories": judge_batches * max(sizes), "peak_cm1": e_ref * CM,
+                  "half_max_centre_cm1": None if h_ref is None else h_ref * CM},
         "plain": plain, "learned": learned,
         "flow": {"layers": layers, "width": width, "params": int(FLOW_PARAMS(prob.F, width, layers)),
                  "n_train": n_train, "epochs": epochs, "batch": batch, "lr": lr, "alpha": alpha,
@@ -256,6 +392,245 @@ def learned_study(scivr, inputs, peaks, prob, ref_I, sizes, seeds, n_train, laye
                  "ess_median": float(np.median(info["ess"])), "fallbacks": int(sum(1 for u in info["used"] if not u))},
         "sweep_s": {"plain": t_plain, "learned": t_learned},
     }
+
+
+def _jackknife_peaks(peaks, E, T, tots, Gs, scale, ref, tol):
+    """Peaks of the pooled spectrum sum(tots) / sum(Gs) matched to the reference
+    peaks `ref`, each with its jackknife standard error over the batches
+    (leave-one-batch-out spectra); unmatched peaks give None."""
+    tots, Gs = np.asarray(tots), np.asarray(Gs)
+    B = len(Gs)
+
+    def match(I):
+        pk = peaks.find_peaks(E, I, T)
+        out = []
+        for e, _ in ref:
+            d = [abs(e - t) for t, _ in pk]
+            out.append(None if not d or min(d) > tol else pk[int(np.argmin(d))][0])
+        return out
+
+    full = match(scale * tots.sum(axis=0) / Gs.sum())
+    loo = [match(scale * (tots.sum(axis=0) - tots[b]) / (Gs.sum() - Gs[b])) for b in range(B)]
+    res = []
+    for i, e in enumerate(full):
+        xs = [l[i] for l in loo if l[i] is not None]
+        if e is None or len(xs) < B:
+            res.append((e, None))
+            continue
+        xs = np.array(xs)
+        res.append((e, float(np.sqrt((B - 1) / B * np.sum((xs - xs.mean()) ** 2)))))
+    return res
+
+
+def c5_study(scivr, torch, inputs, peaks, n, B=8, seed=303, n_train=32768, layers=4, width=256, epochs=10,
+             batch=4096, lr=1e-3, chunk=2048, frac=0.2, min_ess=0.05, variants=((1.0, 0.1), (0.0, 0.1))):
+    """The F=30 configuration: mixed form + learned proposal against the plain
+    FP64 GPU judge, with Monte Carlo error bars.
+
+    * Judge: the FP64 form on n Husimi points in B batches.
+    * Precision alone: the mixed form on the same points; then both forms
+      again on the points that are good in both (identical good subsets), so
+      their peak difference holds no sampling or flagging difference.
+    * Mixed + learned: a flow trained on the mixed form's contributions of a
+      separate Husimi batch, sampled (defensive mixture) for n points in B
+      batches, importance-weighted.
+    Peaks are those of the judge with I >= frac * max (and >= 5 % for the
+    full list), matched within 20 cm^-1; each carries the jackknife standard
+    error over the B batches."""
+    CM = inputs.CM1_PER_HARTREE
+    pf, _ = inputs.workload("F30_fp64")
+    pm, _ = inputs.workload("F30_mixed")
+    E, T = pf.energies(), pf.total_time
+    scale = pf.dt ** 2 / (2 * np.pi * T)
+    nb = n // B
+    tol = 20.0 / CM
+
+    def propagate(ctx, prob, label):
+        for b0 in range(0, prob.n_steps, chunk):
+            ctx.propagate(b0, min(prob.n_steps, b0 + chunk))
+            torch.cuda.synchronize()
+        print(f"[c5] {label} done", file=sys.stderr, flush=True)
+
+    def batched(prob, fill, label):
+        ctx = scivr.Context(prob, max_traj=nb)
+        tots, Gs, goods, pts = [], [], [], []
+        for b in range(B):
+            ctx.reset_spectrum()
+            fill(ctx, b)
+            propagate(ctx, prob, f"{label} batch {b}")
+            ctx.accumulate()
+            tot, G, ng, _ = ctx.read_totals()
+            tots.append(tot)
+            Gs.append(G)
+            goods.append(ctx.read_state(want_M=False)["good"].astype(bool))
+            pts.append(ctx.read_initial())
+        ctx.close()
+        return tots, Gs, goods, pts
+
+    t0 = time.perf_counter()
+    husimi = lambda ctx, b: ctx.sample_husimi(seed=seed, n_traj=nb, first_index=b * nb)
+    jt, jG, jgood, jpts = batched(pf, husimi, "fp64 judge")
+    t_judge = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    mt, mG, mgood, _ = batched(pm, husimi, "mixed")
+    t_mixed = time.perf_counter() - t0
+    I_judge = scale * np.sum(jt, axis=0) / np.sum(jG)
+    ref_all = peaks.find_peaks(E, I_judge, T)
+    ref = [p for p in ref_all if p[1] >= frac * I_judge.max()]
+
+    # identical good subsets: the points good in both forms, both forms again
+    both = [jg & mg for jg, mg in zip(jgood, mgood)]
+    sub = {}
+    for form, prob in (("fp64", pf), ("mixed", pm)):
+        ctx = scivr.Context(prob, max_traj=max(1, max(int(x.sum()) for x in both)))
+        tots, Gs = [], []
+        for b in range(B):
+            keep = np.flatnonzero(both[b])
+            if keep.size == 0:
+                tots.append(np.zeros(pf.n_energies))
+                Gs.append(0.0)
+                continue
+            p0, q0, logrho = jpts[b]
+            ctx.reset_spectrum()
+            ctx.set_initial(p0[:, keep], q0[:, keep], logrho[keep])
+            propagate(ctx, prob, f"identical subset {form} batch {b}")
+            ctx.accumulate()
+            tot, G, ng, _ = ctx.read_totals()
+            tots.append(tot)
+            Gs.append(G)
+        ctx.close()
+        sub[form] = (tots, Gs)
+    Isub = {f: scale * np.sum(sub[f][0], axis=0) / np.sum(sub[f][1]) for f in sub}
+    ref_sub = [p for p in peaks.find_peaks(E, Isub["fp64"], T) if p[1] >= frac * Isub["fp64"].max()]
+    pk_sub = _jackknife_peaks(peaks, E, T, *sub["mixed"], scale, ref_sub, tol)
+    pk_sub_j = _jackknife_peaks(peaks, E, T, *sub["fp64"], scale, ref_sub, tol)
+
+    # learned proposals, trained on a separate Husimi batch of the mixed form.
+    # The proposal's target is a design choice that leaves the estimator
+    # unbiased (the weights use the proposal's own density): the trajectories'
+    # contributions c_j (temper 1), or c_j^temper, down to the good-trajectory
+    # indicator (temper 0), which asks for the region where trajectories stay
+    # good with equal weight.
+    t0 = time.perf_counter()
+    ctx = scivr.Context(pm, max_traj=max(nb, n_train))
+    ctx.sample_husimi(seed=seed + 1, n_traj=n_train, first_index=1 << 40)
+    propagate(ctx, pm, "training batch")
+    ctx.accumulate()
+    tp0, tq0, _ = ctx.read_initial()
+    tc = ctx.read_contributions()
+    t_batch = time.perf_counter() - t0
+    runs = {}
+    for temper, alpha in variants:
+        c = (tc > 0).astype(np.float64) if temper == 0 else np.where(tc > 0, tc, 0.0) ** temper
+        t0 = time.perf_counter()
+        flow = scivr.Flow(ctx, layers, width, seed=9)
+        loss = flow.train(tp0, tq0, c / c.mean(), epochs=epochs, batch=batch, lr=lr)
+        t_train = time.perf_counter() - t0
+        lt, lG, lgood, ess = [], [], [], []
+        t0 = time.perf_counter()
+        for b in range(B):
+            ctx.reset_spectrum()
+            e_, used = flow.sample(seed=seed + 2, n_traj=nb, first_index=b * nb, alpha=alpha, min_ess_frac=min_ess)
+            ess.append((e_, used))
+            propagate(ctx, pm, f"learned (temper {temper}, alpha {alpha}) batch {b}")
+            ctx.accumulate()
+            tot, G, ng, _ = ctx.read_totals()
+            lt.append(tot)
+            lG.append(G)
+            lgood.append(ng / nb)
+        flow.close()
+        runs[(temper, alpha)] = {"lt": lt, "lG": lG, "lgood": lgood, "ess": ess, "loss": loss, "train_s": t_train,
+                                 "wall_s": time.perf_counter() - t0}
+    ctx.close()
+
+    def compare(pk_test, pk_ref):
+        rows = []
+        for (e_r, s_r), (e_t, s_t) in zip(pk_ref, pk_test):
+            if e_r is None or e_t is None:
+                rows.append({"judge_cm1": None if e_r is None else e_r * CM, "missing": True})
+                continue
+            sig = None if (s_r is None or s_t is None) else float(np.hypot(s_r, s_t)) * CM
+            rows.append({"judge_cm1": e_r * CM, "test_cm1": e_t * CM, "delta_cm1": (e_t - e_r) * CM,
+                         "sigma_cm1": sig})
+        return rows
+
+    # statistics a broad band of close levels keeps stable against Monte Carlo
+    # ripples: the main peak of the spectrum smoothed at twice the time
+    # window's resolution, and the first moment over the judge's band (I >= 5 %
+    # of max), each with the jackknife error over the batches
+    sig = 2.0 * 2.0 * np.pi / T / 2.355
+    band = E[I_judge >= 0.05 * I_judge.max()]
+    lo, hi = float(band.min()), float(band.max())
+
+    def jack(stat, tots, Gs):
+        tots, Gs = np.asarray(tots), np.asarray(Gs)
+        full = stat(scale * tots.sum(axis=0) / Gs.sum())
+        loo = np.array([stat(scale * (tots.sum(axis=0) - tots[b]) / (Gs.sum() - Gs[b])) for b in range(B)])
+        return full, float(np.sqrt((B - 1) / B * np.sum((loo - loo.mean()) ** 2)))
+
+    def main_peak(I):
+        Is = peaks.smooth(E, I, sig)
+        k = int(np.argmax(Is))
+        k = min(max(k, 1), E.size - 2)
+        y0, y1, y2 = Is[k - 1], Is[k], Is[k + 1]
+        return E[k] + 0.5 * (y0 - y2) / (y0 - 2 * y1 + y2) * (E[1] - E[0])
+
+    def cen(I):
+        return peaks.centroid(E, I, lo, hi)
+
+    def stable(tots_t, Gs_t, tots_r, Gs_r):
+        out = {}
+        for name, st in (("smoothed_main_peak", main_peak), ("band_centroid", cen)):
+            (vt, st_t), (vr, st_r) = jack(st, tots_t, Gs_t), jack(st, tots_r, Gs_r)
+            out[name] = {"judge_cm1": vr * CM, "test_cm1": vt * CM, "delta_cm1": (vt - vr) * CM,
+                         "sigma_cm1": float(np.hypot(st_t, st_r)) * CM, "sigma_judge_cm1": st_r * CM,
+                         "sigma_test_cm1": st_t * CM}
+        return out
+
+    # per-energy jackknife variance over the judge's band: judge vs learned at equal N
+    def jvar(tots, Gs):
+        tots, Gs = np.asarray(tots), np.asarray(Gs)
+        loo = np.array([scale * (tots.sum(axis=0) - tots[b]) / (Gs.sum() - Gs[b]) for b in range(B)])
+        return (B - 1) / B * np.sum((loo - loo.mean(axis=0)) ** 2, axis=0)
+
+    inband = I_judge >= 0.05 * I_judge.max()
+    pk_judge = _jackknife_peaks(peaks, E, T, jt, jG, scale, ref, tol)
+    pk_mixed = _jackknife_peaks(peaks, E, T, mt, mG, scale, ref, tol)
+    worst = lambda rows: max([abs(r["delta_cm1"]) for r in rows if not r.get("missing")] or [float("nan")])
+    learned = {}
+    for (temper, alpha), v in runs.items():
+        I_learn = scale * np.sum(v["lt"], axis=0) / np.sum(v["lG"])
+        rows = compare(_jackknife_peaks(peaks, E, T, v["lt"], v["lG"], scale, ref, tol), pk_judge)
+        learned[f"temper_{temper}_alpha_{alpha}"] = {
+            "good_fraction": float(np.mean(v["lgood"])),
+            "variance_ratio_judge_over_learned": float(np.median(jvar(jt, jG)[inband] / jvar(v["lt"], v["lG"])[inband])),
+            "stable_vs_judge": stable(v["lt"], v["lG"], jt, jG),
+            "peaks_vs_judge": {"peaks": rows, "worst_abs_delta_cm1": worst(rows),
+                               "missing": int(sum(1 for r in rows if r.get("missing")))},
+            "rel_rms_vs_judge": float(np.sqrt(np.mean((I_learn - I_judge) ** 2)) / I_judge.max()),
+            "ess": [float(e) for e, _ in v["ess"]], "fallbacks": int(sum(1 for _, u in v["ess"] if not u)),
+            "final_loss": v["loss"], "train_s": v["train_s"], "wall_s": v["wall_s"],
+        }
+    out = {
+        "n_traj": n, "batches": B, "peak_threshold_frac": frac,
+        "judge_peaks_cm1": [e * CM for e, _ in ref], "judge_peaks_5pct": len(ref_all),
+        "good_fraction": {"fp64": float(np.mean(np.concatenate(jgood))), "mixed": float(np.mean(np.concatenate(mgood))),
+                          "both": float(np.mean(np.concatenate(both)))},
+        "smoothing_fwhm_cm1": sig * 2.355 * CM, "band_cm1": [lo * CM, hi * CM],
+        "precision_identical_subset": {"n_traj": int(sum(int(x.sum()) for x in both)),
+                                       "peaks": compare(pk_sub, pk_sub_j), "worst_abs_delta_cm1": None},
+        "stable_precision_identical_subset": stable(*sub["mixed"], *sub["fp64"]),
+        "mixed_vs_judge": {"peaks": compare(pk_mixed, pk_judge)},
+        "stable_mixed_vs_judge": stable(mt, mG, jt, jG),
+        "learned": learned,
+        "flow": {"width": width, "layers": layers, "n_train": n_train, "epochs": epochs,
+                 "min_ess_frac": min_ess, "training_batch_s": t_batch},
+        "wall_s": {"judge": t_judge, "mixed": t_mixed},
+    }
+    for key in ("precision_identical_subset", "mixed_vs_judge"):
+        out[key]["worst_abs_delta_cm1"] = worst(out[key]["peaks"])
+        out[key]["missing"] = int(sum(1 for r in out[key]["peaks"] if r.get("missing")))
+    return out
 
 
 def _energy_summary(run, steps):
@@ -285,6 +660,17 @@ def main():
                     help="also time the exact FFT-autocorrelation Fourier step against the GEMM (1) or not (0)")
     ap.add_argument("--chunk", type=int, default=0,
                     help="propagate in calls of this many time steps, printing progress (0: one call)")
+    ap.add_argument("--cpu-single", type=int, default=64,
+                    help="oracle trajectories for the single-thread CPU rate (0: skip)")
+    ap.add_argument("--c5", type=int, default=0,
+                    help="only run the F=30 mixed + learned vs FP64 judge study on this many trajectories and exit")
+    ap.add_argument("--c5-variants", default="1:0.1,0:0.1",
+                    help="learned-proposal variants of the F=30 study, temper:alpha pairs (temper 0: good indicator)")
+    ap.add_argument("--c5-train", type=int, default=32768, help="training batch of the F=30 study's flows")
+    ap.add_argument("--oracle-full", default="",
+                    help="only time the oracle over this whole workload on the host cores and exit")
+    ap.add_argument("--sweep", default="",
+                    help="only run the throughput sweep of this workload over N = 2^7 .. 2^18 and exit")
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="only copy this many bytes device-to-device (counter calibration) and exit")
     args = ap.parse_args()
@@ -294,6 +680,9 @@ def main():
                           "n_gpus": args.gpus}))
         sys.exit(2)
 
+    if args.oracle_full:  # host cores only
+        print(json.dumps({"oracle_full": oracle_full(args.oracle_full)}))
+        return
     import torch
     from paper_1312_4698_amd import inputs, peaks, scivr
 
@@ -307,6 +696,15 @@ def main():
         b.copy_(a)
         torch.cuda.synchronize()
         print(json.dumps({"copied_bytes": a.numel() * 8}))
+        return
+    if args.c5:
+        vs = tuple(tuple(float(x) for x in v.split(":")) for v in args.c5_variants.split(","))
+        res = c5_study(scivr, torch, inputs, peaks, args.c5, n_train=args.c5_train, variants=vs)
+        print(json.dumps({"c5_study": res}))
+        return
+    if args.sweep:
+        res = x1_sweep(scivr, torch, inputs, args.sweep, range(7, 19))
+        print(json.dumps({"sweep_summary": res}))
         return
     prob, n = inputs.workload(args.workload)
     if args.n_traj:
@@ -334,14 +732,14 @@ def main():
     fl_launch = traj_flops_per_step(prob.F) * traj_steps / launches_per_pass
     achieved = fl_launch / t_launch / 1e12
     big = prob.F > 16
-    src_hash = _source_hash("traj_big.hip" if big else "traj.hip", "traj_common.h")
+    src_hash = _source_hash(*(("traj_big.hip", "traj_common.h") if big else ("traj.hip", "traj_common.h", "group_lu.h")))
     traffic = _profile_traffic(prob.name, src_hash)
     fo_launch = ms_fo / max(n_fo, 1) / 1e3
     fo_fl = fourier_flops(n, prob.n_steps + 1, prob.n_energies)
     mixed = prob.precision == inputs.PRECISION_MIXED
 
     out = {
-        "metric": "trajectory-steps/s at F=9",
+        "metric": f"trajectory-steps/s at F={prob.F}",
         "value": value,
         "unit": "trajectory-steps/s",
         "n_gpus": 1,
@@ -407,28 +805,32 @@ def main():
         print("[bench] learned-proposal study", file=sys.stderr, flush=True)
         sizes = [1 << k for k in range(10, 19)]
         out["learned_proposal"] = learned_study(scivr, inputs, peaks, prob, plain["I"], sizes,
-                                                seeds=(11, 12, 13, 14, 15),
+                                                seeds=tuple(range(11, 31)),
                                                 n_train=65536, layers=4, width=128, epochs=20, batch=4096, lr=1e-3,
                                                 alpha=0.1)
-        out["learned_proposal"]["reference"] = (f"plain FP64 spectrum of the timed run: {args.steps} batches of {n} "
-                                            f"Husimi trajectories")
         lp = out["learned_proposal"]
         vp, vm = out["plain_fp64"]["value"], value
         n_plain, n_learn = lp["plain"]["N_to_1cm"], lp["learned"]["N_to_1cm"]
         train_s = lp["flow"]["train_s"] + lp["flow"]["n_train"] * prob.n_steps / vm
+        both = n_plain is not None and n_learn is not None
         out["time_to_1cm"] = {
-            "plain_fp64_s": None if n_plain is None else n_plain * prob.n_steps / vp,
-            "plain_fp64_lower_bound_s": sizes[-1] * prob.n_steps / vp if n_plain is None else None,
-            "mixed_learned_s": None if n_learn is None else n_learn * prob.n_steps / vm + train_s,
-            "mixed_learned_training_s": train_s,
             "equal_variance_speedup": lp["variance_ratio_plain_over_learned"] * vm / vp,
             "equal_variance_energy_ratio": (
                 None if not (out["energy"] and out["plain_fp64"]["energy"]) else
                 lp["variance_ratio_plain_over_learned"] * out["plain_fp64"]["energy"]["J_per_step"]
                 / out["energy"]["J_per_step"]),
+            # only when both sides reach 1 cm^-1 within the sweep
+            "plain_fp64_s": n_plain * prob.n_steps / vp if both else None,
+            "mixed_learned_s": n_learn * prob.n_steps / vm + train_s if both else None,
+            "fit_plain_fp64_s": (None if lp["plain"]["N_to_1cm_fit"] is None else
+                                 lp["plain"]["N_to_1cm_fit"] * prob.n_steps / vp),
+            "fit_mixed_learned_s": (None if lp["learned"]["N_to_1cm_fit"] is None else
+                                    lp["learned"]["N_to_1cm_fit"] * prob.n_steps / vm + train_s),
+            "mixed_learned_training_s": train_s,
             "note": ("plain: FP64 path with Husimi sampling; mixed_learned: mixed path with the learned proposal, "
                      "including its training batch and training time; equal_variance_speedup = (plain/learned "
-                     "spectrum variance at equal N) x (mixed/plain throughput)"),
+                     "spectrum variance at equal N) x (mixed/plain throughput); fit_*: from the N^-1/2 fit of the "
+                     "median peak error"),
         }
     if args.fft:
         # a separate wall-time line: the Fourier step of one batch of each form
@@ -449,7 +851,7 @@ def main():
     if args.cpu_sample > 0:
         print(f"[bench] cpu baseline: oracle on {args.cpu_sample} trajectories", file=sys.stderr, flush=True)
         pprob = prob.replace(precision=inputs.PRECISION_FP64)
-        out["cpu_baseline"] = cpu_baseline(pprob, args.cpu_sample, seed=77)
+        out["cpu_baseline"] = cpu_baseline(pprob, args.cpu_sample, seed=77, n_single=args.cpu_single)
     print(json.dumps(out))
 
 

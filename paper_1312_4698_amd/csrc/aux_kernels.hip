@@ -72,7 +72,9 @@ __global__ void weights_kernel(const ProblemDev *__restrict__ P, int F, const do
     if (j < npad) {
         double w = 0.0, r = 0.0;
         if (j < n && good_row[j] != 0.0) {
-            w = ldexp(exp(-logrho[j] - P->F_log_2pi), -2 * (int)escale_row[j]);
+            // in the log domain: for a point far in the sampling density's tail
+            // exp(-ln rho) alone overflows while the scaled weight is moderate
+            w = exp(-logrho[j] - P->F_log_2pi - 2.0 * escale_row[j] * 0.69314718055994530942);
             g = true;
             r = 1.0;
             if (!husimi) {

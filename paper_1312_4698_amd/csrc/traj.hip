@@ -90,8 +90,8 @@ struct alignas(16) GroupLds : GroupCore<F, MULTI> {
 // MIXED = true: the trajectory (p, q), the potential, gradient and Hessian
 // diagonal and the action (Kahan-compensated) in FP32; the tangent columns,
 // det(A), det(M) and the phase branch stay in FP64; the amplitude, scaled by a
-// per-trajectory power of two 2^e (e = floor(-log2 |<chi|z_0>|) + 3) so that
-// both FP16 parts of its components stay normal, is stored as FP16 hi/lo planes
+// per-trajectory power of two 2^e (e = min(floor(-log2 |<chi|z_0>|) + 3, 15)) so
+// that both FP16 parts of its components stay normal and none can overflow, is stored as FP16 hi/lo planes
 // [re_hi, re_lo, im_hi, im_lo][t / 8][trajectory][t % 8] for the FP16 GEMM.
 // MULTI (FP64 only): amplitudes for each of A.n_refs reference states of the
 // problem's widths, [t][ref][trajectory].
@@ -261,9 +261,10 @@ traj_kernel(TrajArgs A, const ProblemDev *__restrict__ P0)
         if constexpr (MIXED) {  // every lane: the ring's lanes store with it
             double ph;
             const double ex0 = overlap(P, ph);
-            // 2^escale: the exact power of two that puts |<chi|z_0>| 2^escale in (4, 8],
-            // so both FP16 parts of every component stay normal (about 22 bits)
-            escale = (int)floor(-ex0 * 1.4426950408889634) + 3;
+            // 2^escale: the power of two that puts |<chi|z_0>| 2^escale in (4, 8], so
+            // both FP16 parts stay normal (about 22 bits), capped at 2^15: since
+            // |<chi|z_t>| <= 1, no later amplitude can then exceed 2^15 < 65504
+            escale = (int)fmin(floor(-ex0 * 1.4426950408889634) + 3.0, 15.0);
         }
         if (c == 0 && live) store_amplitude(P, 0);
     }

@@ -302,7 +302,7 @@ traj_big_kernel(TrajArgs A, const ProblemDev *__restrict__ P0)
         if constexpr (MIXED) {
             double ph;
             const double ex0 = overlap(P, ph);
-            escale = (int)floor(-ex0 * 1.4426950408889634) + 3;
+            escale = (int)fmin(floor(-ex0 * 1.4426950408889634) + 3.0, 15.0);
         }
         store_amplitude(P, 0);
     }

@@ -135,3 +135,29 @@ def test_reference_state_errors(scivr):
     with pytest.raises(scivr.ScivrError, match="EUNSUPPORTED"):
         cm.set_references(np.zeros((1, 2)), np.zeros((1, 2)))
     cm.close()
+
+
+@pytest.mark.parametrize("F", [3, 9])
+def test_reference_spectra_chunked_propagation_identical(scivr, F):
+    """Continuations of the multi-reference kernel (the ring part-filled at the
+    chunk ends) give the same amplitudes, hence the same spectra, bit for bit."""
+    _say(f"[refs] chunked F={F}")
+    prob = inputs.morse_quartic(F, F, n_steps=300, n_energies=128, e_max=0.1)
+    pe, qe = _refs(prob, 3, 7)
+    out = []
+    for chunks in (None, [1, 77, 150]):
+        ctx = scivr.Context(prob, max_traj=140)
+        ctx.set_references(pe, qe)
+        ctx.sample_husimi(5, 140)
+        if chunks is None:
+            ctx.propagate()
+        else:
+            b = 0
+            for e in chunks + [prob.n_steps]:
+                ctx.propagate(b, e)
+                b = e
+        ctx.accumulate()
+        out.append([ctx.read_spectrum(m)[0] for m in range(4)])
+        ctx.close()
+    for m in range(4):
+        assert np.array_equal(out[0][m], out[1][m]), m
