@@ -77,6 +77,38 @@ __device__ __attribute__((always_inline)) inline double readlane_f64(double v, i
     return __hiloint2double(hi, lo);
 }
 
+// v from the lane selected by the DPP control CTRL (rows in ROW_MASK), 0 where
+// there is no source lane.
+template <int CTRL, int ROW_MASK>
+__device__ __attribute__((always_inline)) inline float dpp_src(float v)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROW_MASK, 0xf, false));
+}
+template <int CTRL, int ROW_MASK>
+__device__ __attribute__((always_inline)) inline double dpp_src(double v)
+{
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROW_MASK, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROW_MASK, 0xf, false);
+    return __hiloint2double(hi, lo);
+}
+
+// Sum of v over lanes 0..31, returned to every lane: prefix sums within each
+// row of 16 lanes (row shifts 1, 2, 4, 8), then row 0's total added into
+// row 1 (row broadcast 15), read from lane 31.
+template <typename T>
+__device__ __attribute__((always_inline)) inline T wave_sum32(T v)
+{
+    v += dpp_src<0x111, 0xf>(v);
+    v += dpp_src<0x112, 0xf>(v);
+    v += dpp_src<0x114, 0xf>(v);
+    v += dpp_src<0x118, 0xf>(v);
+    v += dpp_src<0x142, 0xa>(v);
+    if constexpr (sizeof(T) == 8)
+        return readlane_f64(v, 31);
+    else
+        return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 31));
+}
+
 // Lane of the live row at position ppos (exactly one).
 __device__ __attribute__((always_inline)) inline int pivot_lane(bool alive, int pos, int ppos)
 {
@@ -106,6 +138,10 @@ __device__ __attribute__((always_inline)) inline double lu_det_rows(double (&a)[
         const bool isp = alive && pos == ppos;
         const double pk = readlane_f64(a[k], pl);
         det *= (ppos != k) ? -pk : pk;
+        // the product is taken here, in a vector register: left to the
+        // scheduler, the 2N pivot halves stay live in scalar registers until
+        // the end and push the kernel into scalar spills
+        asm volatile("" : "+v"(det));
         pos = (alive && pos == k) ? ppos : pos;
         alive = alive && !isp;
         if (k + 1 < N) {
@@ -114,8 +150,18 @@ __device__ __attribute__((always_inline)) inline double lu_det_rows(double (&a)[
             const double l = a[k] * rcp_nr(pk);
             a[k + 1] = fma(-l, readlane_f64(a[k + 1], pl), a[k + 1]);
             win = wave_max_u32(alive ? pivot_key32(fabs(a[k + 1]), pos) : 0u);
+            // the pivot row arrives four entries at a time, so several
+            // readlanes are in flight before their scalar registers are used
 #pragma unroll
-            for (int jj = k + 2; jj < N; ++jj) a[jj] = fma(-l, readlane_f64(a[jj], pl), a[jj]);
+            for (int j0 = k + 2; j0 < N; j0 += 4) {
+                double b[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    if (j0 + u < N) b[u] = readlane_f64(a[j0 + u], pl);
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    if (j0 + u < N) a[j0 + u] = fma(-l, b[u], a[j0 + u]);
+            }
         }
     }
     return det;
@@ -141,6 +187,7 @@ __device__ __attribute__((always_inline)) inline void lu_det_rows_complex(double
         const double ni = zr * pi + zi * pr;
         zr = (ppos != k) ? -nr : nr;
         zi = (ppos != k) ? -ni : ni;
+        asm volatile("" : "+v"(zr), "+v"(zi));  // as in lu_det_rows
         pos = (alive && pos == k) ? ppos : pos;
         alive = alive && !isp;
         if (k + 1 < N) {
@@ -154,10 +201,20 @@ __device__ __attribute__((always_inline)) inline void lu_det_rows_complex(double
             }
             win = wave_max_u32(alive ? pivot_key32(fma(ar[k + 1], ar[k + 1], ai[k + 1] * ai[k + 1]), pos) : 0u);
 #pragma unroll
-            for (int jj = k + 2; jj < N; ++jj) {
-                const double br = readlane_f64(ar[jj], pl), bi = readlane_f64(ai[jj], pl);
-                ar[jj] = fma(-lr, br, fma(li, bi, ar[jj]));
-                ai[jj] = fma(-lr, bi, fma(-li, br, ai[jj]));
+            for (int j0 = k + 2; j0 < N; j0 += 2) {
+                double br[2], bi[2];
+#pragma unroll
+                for (int u = 0; u < 2; ++u)
+                    if (j0 + u < N) {
+                        br[u] = readlane_f64(ar[j0 + u], pl);
+                        bi[u] = readlane_f64(ai[j0 + u], pl);
+                    }
+#pragma unroll
+                for (int u = 0; u < 2; ++u)
+                    if (j0 + u < N) {
+                        ar[j0 + u] = fma(-lr, br[u], fma(li, bi[u], ar[j0 + u]));
+                        ai[j0 + u] = fma(-lr, bi[u], fma(-li, br[u], ai[j0 + u]));
+                    }
             }
         }
     }
@@ -173,8 +230,10 @@ traj_big_kernel(TrajArgs A, const ProblemDev *__restrict__ P0)
     constexpr int N2 = 2 * F;
     constexpr int RS = BigLds<F>::RS;
     constexpr int FP = F + (F & 1);
+    constexpr bool SM_MFMA = N2 < 64;  // a spare product column for sum_k Lambda_ik q_k^2
     __shared__ BigLds<F> L;
-    __shared__ R qv[FP], pm[FP], phd[FP], pv[FP];
+    __shared__ R qv[FP], pm[FP];
+    __shared__ double2 qh[F];  // (4 q_i, h_i) of the kick's Hessian diagonal terms
 
     const int lane = threadIdx.x;
     const ProblemDev *__restrict__ P = P0;
@@ -247,44 +306,43 @@ traj_big_kernel(TrajArgs A, const ProblemDev *__restrict__ P0)
     }
     lds_order();
 
-    // exponent and phase of <chi|p,q> of the published state
-    auto overlap = [&](auto PP, double &ph) -> double {
-        double ex = 0.0;
-        ph = 0.0;
-#pragma unroll
-        for (int i = 0; i < F; ++i) {
-            const double qi = (double)qv[i], pi = (double)pm[i];
-            const double dqe = PP->q_eq[i] - qi;
-            const double dpe = PP->p_eq[i] - pi;
-            ex += -0.25 * PP->gamma[i] * dqe * dqe - dpe * dpe * PP->inv4gamma[i];
-            ph += 0.5 * dqe * (PP->p_eq[i] + pi);
+    // exponent and phase of <chi_m|p,q> (reference state m; m = 0 is chi): each
+    // mode lane forms its own terms from its (q, p), summed across the wave
+    // (every lane calls this)
+    const double g4c = 0.25 * P->gamma[cm], i4gc = P->inv4gamma[cm];
+    const double rq0 = P->ref_q[0][cm], rp0 = P->ref_p[0][cm];
+    auto overlap = [&](auto PP, int m, double &ph) -> double {
+        double ex = 0.0, phm = 0.0;
+        if (modeLane) {
+            const double qi = (double)qc, pi = (double)pc;
+            const double rq = m == 0 ? rq0 : PP->ref_q[m][lane], rp = m == 0 ? rp0 : PP->ref_p[m][lane];
+            const double dqe = rq - qi, dpe = rp - pi;
+            ex = -g4c * dqe * dqe - dpe * dpe * i4gc;
+            phm = 0.5 * dqe * (rp + pi);
         }
-        return ex;
+        ph = wave_sum32(phm);
+        return wave_sum32(ex);
     };
-    auto store_amplitude = [&](auto PP, int t) {
+    // amplitude of time sample t (lane 0 stores; ex0, ph0 are reference 0's
+    // overlap terms, the others are formed here with every lane)
+    auto store_amplitude = [&](auto PP, int t, double ex0, double ph0) {
         if constexpr (!MIXED) {
-            // each reference state's amplitude, [t][ref][trajectory]; ref 0 is chi
+            // each reference state's amplitude, [t][ref][trajectory]
             for (int m = 0; m < A.n_refs; ++m) {
-                double ex = 0.0, ph = 0.0;
-#pragma unroll
-                for (int i = 0; i < F; ++i) {
-                    const double qi = (double)qv[i], pi = (double)pm[i];
-                    const double dqe = PP->ref_q[m][i] - qi;
-                    const double dpe = PP->ref_p[m][i] - pi;
-                    ex += -0.25 * PP->gamma[i] * dqe * dqe - dpe * dpe * PP->inv4gamma[i];
-                    ph += 0.5 * dqe * (PP->ref_p[m][i] + pi);
+                double ex = ex0, ph = ph0;
+                if (m > 0) ex = overlap(PP, m, ph);
+                if (lane == 0) {
+                    double s, co;
+                    dsincos(ph + S.value() + phi, &PP->mc, &s, &co);
+                    const double mag = dexp(ex, &PP->mc);
+                    double2 r;
+                    r.x = good ? mag * co : 0.0;
+                    r.y = good ? mag * s : 0.0;
+                    A.amp[((int64_t)t * A.n_refs + m) * NP + jr] = r;
                 }
-                double s, co;
-                dsincos(ph + S.value() + phi, &PP->mc, &s, &co);
-                const double mag = dexp(ex, &PP->mc);
-                double2 r;
-                r.x = good ? mag * co : 0.0;
-                r.y = good ? mag * s : 0.0;
-                A.amp[((int64_t)t * A.n_refs + m) * NP + jr] = r;
             }
-        } else {
-            double ph;
-            const double ex = overlap(PP, ph);
+        } else if (lane == 0) {
+            const double ex = ex0, ph = ph0;
             double s, co;
             dsincos(ph + S.value() + phi, &PP->mc, &s, &co);
             const double mag = ldexp(dexp(ex, &PP->mc), escale);
@@ -298,13 +356,11 @@ traj_big_kernel(TrajArgs A, const ProblemDev *__restrict__ P0)
         }
     };
 
-    if (A.step_begin == 0 && lane == 0) {
-        if constexpr (MIXED) {
-            double ph;
-            const double ex0 = overlap(P, ph);
-            escale = (int)fmin(floor(-ex0 * 1.4426950408889634) + 3.0, 15.0);
-        }
-        store_amplitude(P, 0);
+    if (A.step_begin == 0) {
+        double ph0;
+        const double ex0 = overlap(P, 0, ph0);
+        if constexpr (MIXED) escale = (int)fmin(floor(-ex0 * 1.4426950408889634) + 3.0, 15.0);
+        store_amplitude(P, 0, ex0, ph0);
     }
 
     for (int step = A.step_begin; step < A.step_end; ++step) {
@@ -314,15 +370,7 @@ traj_big_kernel(TrajArgs A, const ProblemDev *__restrict__ P0)
             ConstProblem Pk = opaque(P0);
             // ---- drift ----
             const double h = Pk->hd[s];
-            if (lane == 0) {
-                R kin = 0;
-#pragma unroll
-                for (int i = 0; i < F; ++i) {
-                    const R pi = pm[i];
-                    kin += (R)0.5 * pi * pi;
-                }
-                S.add(h * (double)kin);
-            }
+            S.add(h * (double)wave_sum32(modeLane ? (R)0.5 * pc * pc : (R)0));
             if (modeLane) qc = fma((R)h, pc, qc);
 #pragma unroll
             for (int i = 0; i < F; ++i) dq[i] = fma(h, dp[i], dq[i]);
@@ -330,43 +378,19 @@ traj_big_kernel(TrajArgs A, const ProblemDev *__restrict__ P0)
             if (modeLane) qv[lane] = qc;
             lds_order();
             if (s == 3) break;
-            // ---- kick: mode terms on lanes < F, shared through LDS ----
+            // ---- kick ----
             const double hk = Pk->hc[s];
-            if (modeLane) {
-                R sm = 0;
-#pragma unroll
-                for (int i = 0; i < F; ++i) {
-                    const R qi = qv[i];
-                    sm = fma((R)L.lam[lane * F + i], qi * qi, sm);
-                }
-                R e;
-                if constexpr (MIXED)
-                    e = expf(-ac * qc);
-                else
-                    e = dexp(-ac * qc, &Pk->mc);
-                const R one_e = (R)1 - e;
-                const R gc = kc * qc + (R)2 * Dc * ac * e * one_e + (R)2 * qc * sm;
-                const R hc = kc + (R)2 * Dc * ac * ac * e * ((R)2 * e - (R)1) + (R)2 * sm;
-                const R vc = (R)0.5 * kc * qc * qc + Dc * one_e * one_e + (R)0.5 * qc * qc * sm;
-                pc = fma(-(R)hk, gc, pc);
-                phd[lane] = hc;
-                pv[lane] = vc;
-                pm[lane] = pc;
-            }
-            lds_order();
-            if (lane == 0) {
-                R V = 0;
-#pragma unroll
-                for (int i = 0; i < F; ++i) V += pv[i];
-                S.add(-hk * (double)V);
-            }
-            // tangent kick of every column: dp -= hk (h o dq + 4 q o W), W = Lambda (q o dq),
-            // the 32 x 32 by 32 x 64 product on the matrix cores (v_mfma_f64_16x16x4f64:
+            // the product W = Lambda (q o dQ) of the tangent kick on the matrix
+            // cores, a 32 x 32 by 32 x 64 FP64 product (v_mfma_f64_16x16x4f64:
             // A[i][k] in lane i + 16 k, B[k][j] in lane j + 16 k, D[i][j] in lane
-            // j + 16 (i mod 4), register i / 4); operands and result pass through LDS
+            // j + 16 (i mod 4), register i / 4); operands and result pass through
+            // LDS.  Column 2F, when there is one, carries q o q, so that row i of
+            // its product is the mode term sum_k Lambda_ik q_k^2.
 #pragma unroll
-            for (int i = 0; i < 32; ++i)
-                L.U[i * US + lane] = (i < F && colLane) ? (double)qv[i < F ? i : 0] * dq[i < F ? i : 0] : 0.0;
+            for (int i = 0; i < 32; ++i) {
+                const double qi = (double)qv[i < F ? i : 0];
+                L.U[i * US + lane] = (i >= F) ? 0.0 : colLane ? qi * dq[i < F ? i : 0] : (SM_MFMA && lane == N2) ? qi * qi : 0.0;
+            }
             lds_order();
             d4 acc[2][4];
 #pragma unroll
@@ -392,11 +416,41 @@ traj_big_kernel(TrajArgs A, const ProblemDev *__restrict__ P0)
 #pragma unroll
                     for (int r = 0; r < 4; ++r) L.U[(16 * ib + 4 * r + kg) * US + 16 * cb + li] = acc[ib][cb][r];
             lds_order();
+            // mode terms on lanes < F: gradient, Hessian diagonal and potential
+            R vc = 0;
+            if (modeLane) {
+                R sm;
+                if constexpr (SM_MFMA) {
+                    sm = (R)L.U[lane * US + N2];
+                } else {
+                    sm = 0;
+#pragma unroll
+                    for (int i = 0; i < F; ++i) {
+                        const R qi = qv[i];
+                        sm = fma((R)L.lam[lane * F + i], qi * qi, sm);
+                    }
+                }
+                R e;
+                if constexpr (MIXED)
+                    e = expf(-ac * qc);
+                else
+                    e = dexp(-ac * qc, &Pk->mc);
+                const R one_e = (R)1 - e;
+                const R gc = kc * qc + (R)2 * Dc * ac * e * one_e + (R)2 * qc * sm;
+                const R hc = kc + (R)2 * Dc * ac * ac * e * ((R)2 * e - (R)1) + (R)2 * sm;
+                vc = (R)0.5 * kc * qc * qc + Dc * one_e * one_e + (R)0.5 * qc * qc * sm;
+                pc = fma(-(R)hk, gc, pc);
+                qh[lane] = make_double2(4.0 * (double)qc, (double)hc);
+                pm[lane] = pc;
+            }
+            S.add(-hk * (double)wave_sum32(vc));
+            lds_order();
+            // tangent kick of every column: dp -= hk (h o dq + 4 q o W)
             if (colLane) {
 #pragma unroll
                 for (int i = 0; i < F; ++i) {
-                    const double qi = (double)qv[i];
-                    dp[i] = fma(-hk, fma((double)phd[i], dq[i], 4.0 * qi * L.U[i * US + lane]), dp[i]);
+                    const double2 g = qh[i];
+                    dp[i] = fma(-hk, fma(g.y, dq[i], g.x * L.U[i * US + lane]), dp[i]);
                 }
             }
             lds_order();
@@ -462,6 +516,8 @@ traj_big_kernel(TrajArgs A, const ProblemDev *__restrict__ P0)
         }
 
         // continuous branch of the prefactor phase, as in the small-F kernel
+        double ph0;
+        const double ex0 = overlap(Ps, 0, ph0);
         if (lane == 0) {
             int ex;
             (void)frexp(fmax(fabs(dAr), fabs(dAi)), &ex);
@@ -476,8 +532,8 @@ traj_big_kernel(TrajArgs A, const ProblemDev *__restrict__ P0)
             prev_i = dAi;
             phi = 0.5 * (theta - Ps->sum_gamma * t);
             if (!isfinite(phi) || !isfinite(S.value())) good = false;
-            store_amplitude(Ps, stp);
         }
+        store_amplitude(Ps, stp, ex0, ph0);
     }
 
     // ---- save the state ----
