@@ -67,16 +67,18 @@ def _source_hash(*names):
     return h.hexdigest()[:16]
 
 
-def _profile_traffic(kernel_prefix: str, src_hash: str):
+def _profile_traffic(kernel_prefix: str, src_hash: str, n_launch: int):
     """HBM bytes per launch from a committed rocprofv3 counter summary, if it
-    was taken on the current kernel source; else None."""
+    was taken on the current kernel source with as many trajectories per
+    launch; else None."""
     path = os.path.join(ROOT, "profiles", f"traj_{kernel_prefix}_counters.txt")
     if not os.path.exists(path):
         return None
     txt = open(path).read()
     m = re.search(r"source_hash:\s*(\w+)", txt)
     b = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", txt)
-    if not m or not b or m.group(1) != src_hash:
+    t = re.search(r"trajectories_per_launch:\s*(\d+)", txt)
+    if not m or not b or m.group(1) != src_hash or (t and int(t.group(1)) != n_launch):
         return None
     return float(b.group(1))
 
@@ -733,7 +735,7 @@ def main():
     achieved = fl_launch / t_launch / 1e12
     big = prob.F > 16
     src_hash = _source_hash(*(("traj_big.hip", "traj_common.h") if big else ("traj.hip", "traj_common.h", "group_lu.h")))
-    traffic = _profile_traffic(prob.name, src_hash)
+    traffic = _profile_traffic(prob.name, src_hash, n)
     fo_launch = ms_fo / max(n_fo, 1) / 1e3
     fo_fl = fourier_flops(n, prob.n_steps + 1, prob.n_energies)
     mixed = prob.precision == inputs.PRECISION_MIXED
