@@ -779,6 +779,14 @@ def main():
             "peak_TFLOPs": F16_MFMA_PEAK_TFLOPS / 3.0 if mixed else FP64_MFMA_PEAK_TFLOPS,
             "launch_ms": fo_launch * 1e3,
         },
+        "composite_roofline": {
+            # sum over the step's parts of (algorithmic flops / that part's peak), over the measured step time
+            "frac": (traj_flops_per_step(prob.F) * traj_steps / (FP64_VALU_PEAK_TFLOPS * 1e12)
+                     + fo_fl * n_fo / args.steps / ((F16_MFMA_PEAK_TFLOPS / 3.0 if mixed else FP64_MFMA_PEAK_TFLOPS) * 1e12))
+                    / (ms_step / 1e3),
+            "parts": "trajectory kernel on the FP64 vector peak; Fourier step on "
+                     + ("the dense FP16 MFMA peak / 3" if mixed else "the FP64 MFMA peak"),
+        },
         "n_good_fraction": main_run["n_good"] / max(main_run["n_total"], 1),
         "energy": _energy_summary(main_run, args.steps),
         "cpu_baseline": None,
