@@ -13,18 +13,20 @@
 //    staged through LDS between the column-per-lane and the MFMA layouts;
 //  * det(A) of the Herman-Kluk prefactor matrix of Eq. (5) and det(M) (the
 //    stability monitor after Eq. (5)) are taken as the determinants of the
-//    transposes: lane c < 2F's own column is row c of M^T, and lane i < F
-//    forms column i of A from its own column and column F + i, which it reads
-//    from an LDS copy of M (written column by column; each lane also reloads
-//    its column from it afterwards, so the register copy is dead while the
-//    eliminations run).  Gaussian elimination with partial pivoting runs
-//    across the lanes, one row per lane:
-//    a wave-wide DPP maximum over packed (|a|, position) keys picks each
-//    pivot (the trajectory is the whole wave, so the pivot is wave-uniform)
-//    and the pivot row reaches every lane through readlane into scalar
-//    registers, with no LDS round trip in the elimination;
-//  * lane 0 keeps the action, the continuous prefactor phase and writes the
-//    amplitude of the time sample.
+//    transposes: lane c < 2F's own column is row c of M^T; row i of A^T
+//    (column i of A) has its real parts in lane i and its imaginary parts in
+//    lane 32 + i, both formed from columns i and F + i of an LDS copy of M
+//    (written column by column; each lane also reloads its column from it
+//    afterwards, so the register copy is dead while the eliminations run).
+//    Gaussian elimination with partial pivoting runs across the lanes, one
+//    row (or one part of a complex row) per lane: a wave-wide DPP maximum
+//    over packed (|a|, position) keys picks each pivot (the trajectory is the
+//    whole wave, so the pivot is wave-uniform) and the pivot row reaches
+//    every lane through readlane into scalar registers, with no LDS round
+//    trip in the elimination;
+//  * the action, the overlap terms and the continuous prefactor phase are
+//    summed across the mode lanes; lane 0 writes the amplitude of the time
+//    sample.
 // The state layout, the branch tracking and the amplitude storage (FP64
 // time-major, or FP16 hi/lo planes in the mixed form) are the small-F
 // kernel's.
@@ -167,22 +169,39 @@ __device__ __attribute__((always_inline)) inline double lu_det_rows(double (&a)[
     return det;
 }
 
-// det of the complex N x N matrix whose row `pos` lives in (ar, ai) of the
-// active lanes; pivot on |a_k|^2, otherwise as lu_det_rows.
+// The value of v in lane (lane & 31) and in lane (lane & 31) + 32, to every
+// lane: two v_permlane32_swap, one per 32-bit half (each swaps the upper half
+// of one copy with the lower half of the other).
+__device__ __attribute__((always_inline)) inline void half_pair(double v, double &lower, double &upper)
+{
+    const auto a = __builtin_amdgcn_permlane32_swap(__double2loint(v), __double2loint(v), false, false);
+    const auto b = __builtin_amdgcn_permlane32_swap(__double2hiint(v), __double2hiint(v), false, false);
+    lower = __hiloint2double(b[0], a[0]);
+    upper = __hiloint2double(b[1], a[1]);
+}
+
+// det of the complex N x N matrix (N <= 32) whose row `pos` has its real
+// parts in x[] of lane pos and its imaginary parts in x[] of lane pos + 32
+// (`active` on both lanes of rows 0..N-1; `imag` on the upper half).  Pivot
+// on |a_k|^2 (keys from the real-part lanes), otherwise as lu_det_rows.  Each
+// lane updates one part, so every entry costs the pivot row's four readlanes
+// and two FMAs per lane; a whole complex row per lane would take four FMAs
+// and leave the upper half of the wave idle.  Every lane returns det.
 template <int N>
-__device__ __attribute__((always_inline)) inline void lu_det_rows_complex(double (&ar)[N], double (&ai)[N],
-                                                                          bool active, int pos, double &dr,
-                                                                          double &di)
+__device__ __attribute__((always_inline)) inline void lu_det_rows_complex_split(double (&x)[N], bool active, int pos,
+                                                                                bool imag, double &dr, double &di)
 {
     bool alive = active;
     double zr = 1.0, zi = 0.0;
-    unsigned win = wave_max_u32(alive ? pivot_key32(fma(ar[0], ar[0], ai[0] * ai[0]), pos) : 0u);
+    double re, im;  // this row's entry in the column being eliminated
+    half_pair(x[0], re, im);
+    unsigned win = wave_max_u32((alive && !imag) ? pivot_key32(fma(re, re, im * im), pos) : 0u);
 #pragma unroll
     for (int k = 0; k < N; ++k) {
         const int ppos = 63 - (int)(win & 63u);
-        const int pl = pivot_lane(alive, pos, ppos);
+        const int pl = pivot_lane(alive && !imag, pos, ppos);  // the pivot row's real-part lane
         const bool isp = alive && pos == ppos;
-        const double pr = readlane_f64(ar[k], pl), pi = readlane_f64(ai[k], pl);
+        const double pr = readlane_f64(x[k], pl), pi = readlane_f64(x[k], pl + 32);
         const double nr = zr * pr - zi * pi;
         const double ni = zr * pi + zi * pr;
         zr = (ppos != k) ? -nr : nr;
@@ -192,29 +211,30 @@ __device__ __attribute__((always_inline)) inline void lu_det_rows_complex(double
         alive = alive && !isp;
         if (k + 1 < N) {
             const double inv = rcp_nr(fma(pr, pr, pi * pi));
-            const double lr = (ar[k] * pr + ai[k] * pi) * inv;  // rows out of play: as in lu_det_rows
-            const double li = (ai[k] * pr - ar[k] * pi) * inv;
+            const double lr = (re * pr + im * pi) * inv;  // rows out of play: as in lu_det_rows
+            const double li = (im * pr - re * pi) * inv;
+            // x -= l b: the real part loses lr br - li bi, the imaginary part
+            // lr bi + li br; both as fma(-u, br, fma(v, bi, x)), so every lane
+            // takes the broadcast operands in the same order
+            const double u = imag ? li : lr, v = imag ? -lr : li;
             {
-                const double br = readlane_f64(ar[k + 1], pl), bi = readlane_f64(ai[k + 1], pl);
-                ar[k + 1] = fma(-lr, br, fma(li, bi, ar[k + 1]));
-                ai[k + 1] = fma(-lr, bi, fma(-li, br, ai[k + 1]));
+                const double br = readlane_f64(x[k + 1], pl), bi = readlane_f64(x[k + 1], pl + 32);
+                x[k + 1] = fma(-u, br, fma(v, bi, x[k + 1]));
             }
-            win = wave_max_u32(alive ? pivot_key32(fma(ar[k + 1], ar[k + 1], ai[k + 1] * ai[k + 1]), pos) : 0u);
+            half_pair(x[k + 1], re, im);
+            win = wave_max_u32((alive && !imag) ? pivot_key32(fma(re, re, im * im), pos) : 0u);
 #pragma unroll
             for (int j0 = k + 2; j0 < N; j0 += 2) {
                 double br[2], bi[2];
 #pragma unroll
-                for (int u = 0; u < 2; ++u)
-                    if (j0 + u < N) {
-                        br[u] = readlane_f64(ar[j0 + u], pl);
-                        bi[u] = readlane_f64(ai[j0 + u], pl);
+                for (int w = 0; w < 2; ++w)
+                    if (j0 + w < N) {
+                        br[w] = readlane_f64(x[j0 + w], pl);
+                        bi[w] = readlane_f64(x[j0 + w], pl + 32);
                     }
 #pragma unroll
-                for (int u = 0; u < 2; ++u)
-                    if (j0 + u < N) {
-                        ar[j0 + u] = fma(-lr, br[u], fma(li, bi[u], ar[j0 + u]));
-                        ai[j0 + u] = fma(-lr, bi[u], fma(-li, br[u], ai[j0 + u]));
-                    }
+                for (int w = 0; w < 2; ++w)
+                    if (j0 + w < N) x[j0 + w] = fma(-u, br[w], fma(v, bi[w], x[j0 + w]));
             }
         }
     }
@@ -245,6 +265,13 @@ traj_big_kernel(TrajArgs A, const ProblemDev *__restrict__ P0)
     const int cm = modeLane ? lane : 0;
 
     const R kc = (R)P->k[cm], Dc = (R)P->D[cm], ac = (R)P->a[cm];
+    // the prefactor matrix's rows: lane rc and lane 32 + rc hold row rc of A^T
+    const bool imagLane = lane >= 32;
+    const bool rowLane = (lane & 31) < F;
+    const int rc = rowLane ? (lane & 31) : 0;
+    const double sgr = P->sqrt_gamma[rc], isgr = P->inv_sqrt_gamma[rc];
+    const double alphaA = imagLane ? -sgr : isgr, betaA = imagLane ? isgr : sgr;
+    const int colU = imagLane ? rc : F + rc, colV = imagLane ? F + rc : rc;
     constexpr int US = BigLds<F>::US;
     const int li = lane & 15, kg = lane >> 4;
     // A-operand fragments of Lambda (32 x 32, zero-padded): block (ib, kb) holds
@@ -469,23 +496,24 @@ traj_big_kernel(TrajArgs A, const ProblemDev *__restrict__ P0)
         }
         lds_order();
 
-        // det(A) = det(A^T) and det(M) = det(M^T): lane c < F forms column c of A
-        // from its own column (Mpp[.][c], Mqp[.][c]) and column F + c (Mpq, Mqq)
-        // read from LDS; lane c < 2F holds row c of M^T, its own column
+        // det(A) = det(A^T) and det(M) = det(M^T).  Row c of A^T (column c of A)
+        // has its real parts in lane c and its imaginary parts in lane 32 + c,
+        // formed from columns c and F + c of M in LDS:
+        //   Re A[i][c] = (1/2)[sqrt(g_i) Mqq[i][c] / sqrt(g_c) + Mpp[i][c] sqrt(g_c) / sqrt(g_i)]
+        //   Im A[i][c] = (1/2)[-sqrt(g_i) Mqp[i][c] sqrt(g_c) + Mpq[i][c] / (sqrt(g_i) sqrt(g_c))]
+        // i.e. (1/2)(sqrt(g_i) u alpha + v beta / sqrt(g_i)) with (u, v, alpha, beta)
+        // = (Mqq, Mpp, 1/sqrt(g_c), sqrt(g_c)) or (Mqp, Mpq, -sqrt(g_c), 1/sqrt(g_c)).
+        // Lane c < 2F holds row c of M^T, its own column.
         double dAr, dAi;
         {
-            const double sgc = Ps->sqrt_gamma[cm], isgc = Ps->inv_sqrt_gamma[cm];
-            double are[F], aim[F];
+            double x[F];
 #pragma unroll
             for (int i = 0; i < F; ++i) {
                 const double si = Ps->sqrt_gamma[i], isi = Ps->inv_sqrt_gamma[i];
-                const double mpq = L.T[i * RS + F + cm], mqq = L.T[(F + i) * RS + F + cm];
-                // A[i][c] = (1/2)[sqrt(g_i) Mqq[i][c] / sqrt(g_c) + Mpp[i][c] sqrt(g_c) / sqrt(g_i)]
-                //         + (i/2)[-sqrt(g_i) Mqp[i][c] sqrt(g_c) + Mpq[i][c] / (sqrt(g_i) sqrt(g_c))]
-                are[i] = 0.5 * (si * mqq * isgc + dp[i] * sgc * isi);
-                aim[i] = 0.5 * (-si * dq[i] * sgc + mpq * isi * isgc);
+                const double u = L.T[(F + i) * RS + colU], v = L.T[i * RS + colV];
+                x[i] = 0.5 * (si * u * alphaA + v * isi * betaA);
             }
-            lu_det_rows_complex<F>(are, aim, modeLane, lane, dAr, dAi);
+            lu_det_rows_complex_split<F>(x, rowLane, rc, imagLane, dAr, dAi);
         }
 
         // stability monitor |det(M)^2 - 1| on checked steps
