@@ -44,10 +44,9 @@ template <int F>
 struct alignas(16) BigLds {
     static constexpr int N2 = 2 * F;
     static constexpr int RS = N2 + 1;  // odd row stride of the copy of M
-    static constexpr int US = 65;      // row stride of the kick's 32 x 64 operand / result staging
     union {
         double T[N2 * RS];  // M, row r at T + r RS (after the step)
-        double U[32 * US];  // q o dq, then Lambda (q o dq), row i at U + i US (during the kicks)
+        double U[32];       // the kicks' mode terms sum_k Lambda_ik q_k^2, row i at U + i
     };
     double lam[F * F];  // coupling matrix, row-major, zero diagonal
 };
@@ -169,6 +168,37 @@ __device__ __attribute__((always_inline)) inline double lu_det_rows(double (&a)[
     return det;
 }
 
+// 4 x 4 transpose between the wave's four row groups of 16 lanes and four
+// registers: on return v[c] in row group k holds what v[k] held in row group c
+// (same lane within the group).  Per 32-bit half, v_permlane32_swap on (v0, v2)
+// and (v1, v3), then v_permlane16_swap on (v0, v1) and (v2, v3) (lane layouts
+// checked on the device: permlane32_swap(a, b) gives [a0 a1 b0 b1] and
+// [a2 a3 b2 b3] by row group, permlane16_swap(a, b) gives [a0 b0 a2 b2] and
+// [a1 b1 a3 b3]).
+__device__ __attribute__((always_inline)) inline void group_transpose(double (&v)[4])
+{
+    int lo[4], hi[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        lo[r] = __double2loint(v[r]);
+        hi[r] = __double2hiint(v[r]);
+    }
+    auto stage = [](int (&w)[4]) {
+        auto a = __builtin_amdgcn_permlane32_swap(w[0], w[2], false, false);
+        auto b = __builtin_amdgcn_permlane32_swap(w[1], w[3], false, false);
+        auto c = __builtin_amdgcn_permlane16_swap(a[0], b[0], false, false);
+        auto d = __builtin_amdgcn_permlane16_swap(a[1], b[1], false, false);
+        w[0] = c[0];
+        w[1] = c[1];
+        w[2] = d[0];
+        w[3] = d[1];
+    };
+    stage(lo);
+    stage(hi);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) v[r] = __hiloint2double(hi[r], lo[r]);
+}
+
 // The value of v in lane (lane & 31) and in lane (lane & 31) + 32, to every
 // lane: two v_permlane32_swap, one per 32-bit half (each swaps the upper half
 // of one copy with the lower half of the other).
@@ -272,7 +302,6 @@ traj_big_kernel(TrajArgs A, const ProblemDev *__restrict__ P0)
     const double sgr = P->sqrt_gamma[rc], isgr = P->inv_sqrt_gamma[rc];
     const double alphaA = imagLane ? -sgr : isgr, betaA = imagLane ? isgr : sgr;
     const int colU = imagLane ? rc : F + rc, colV = imagLane ? F + rc : rc;
-    constexpr int US = BigLds<F>::US;
     const int li = lane & 15, kg = lane >> 4;
     // A-operand fragments of Lambda (32 x 32, zero-padded): block (ib, kb) holds
     // Lambda[16 ib + li][4 kb + kg] in this lane
@@ -410,15 +439,11 @@ traj_big_kernel(TrajArgs A, const ProblemDev *__restrict__ P0)
             // the product W = Lambda (q o dQ) of the tangent kick on the matrix
             // cores, a 32 x 32 by 32 x 64 FP64 product (v_mfma_f64_16x16x4f64:
             // A[i][k] in lane i + 16 k, B[k][j] in lane j + 16 k, D[i][j] in lane
-            // j + 16 (i mod 4), register i / 4); operands and result pass through
-            // LDS.  Column 2F, when there is one, carries q o q, so that row i of
-            // its product is the mode term sum_k Lambda_ik q_k^2.
-#pragma unroll
-            for (int i = 0; i < 32; ++i) {
-                const double qi = (double)qv[i < F ? i : 0];
-                L.U[i * US + lane] = (i >= F) ? 0.0 : colLane ? qi * dq[i < F ? i : 0] : (SM_MFMA && lane == N2) ? qi * qi : 0.0;
-            }
-            lds_order();
+            // j + 16 (i mod 4), register i / 4).  Lane c's own column reaches the
+            // B layout, four rows at a time, through a row-group transpose; the
+            // result comes back the same way in the tangent kick below.  Column
+            // 2F, when there is one, carries q o q, so that row i of its product
+            // is the mode term sum_k Lambda_ik q_k^2.
             d4 acc[2][4];
 #pragma unroll
             for (int ib = 0; ib < 2; ++ib)
@@ -426,29 +451,37 @@ traj_big_kernel(TrajArgs A, const ProblemDev *__restrict__ P0)
                 for (int cb = 0; cb < 4; ++cb) acc[ib][cb] = (d4){0.0, 0.0, 0.0, 0.0};
 #pragma unroll
             for (int kb = 0; kb < 8; ++kb) {
-                double b[4];
+                double b[4];  // rows 4 kb .. 4 kb + 3 of this lane's column
 #pragma unroll
-                for (int cb = 0; cb < 4; ++cb) b[cb] = L.U[(4 * kb + kg) * US + 16 * cb + li];
+                for (int r = 0; r < 4; ++r) {
+                    const int i = 4 * kb + r;
+                    const double qi = (double)qv[i < F ? i : 0];
+                    b[r] = (i >= F) ? 0.0 : colLane ? qi * dq[i < F ? i : 0] : (SM_MFMA && lane == N2) ? qi * qi : 0.0;
+                }
+                group_transpose(b);  // b[cb]: column 16 cb + li, row 4 kb + kg
 #pragma unroll
                 for (int ib = 0; ib < 2; ++ib)
 #pragma unroll
                     for (int cb = 0; cb < 4; ++cb)
                         acc[ib][cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(lamA[ib][kb], b[cb], acc[ib][cb], 0, 0, 0);
             }
-            lds_order();
+            if constexpr (SM_MFMA) {
+                // column 2F's rows to LDS for the mode lanes: row 16 ib + 4 r + kg
+                // sits in lane (2F mod 16) + 16 kg, register r of block 2F / 16
+                if (li == (N2 & 15)) {
 #pragma unroll
-            for (int ib = 0; ib < 2; ++ib)
+                    for (int ib = 0; ib < 2; ++ib)
 #pragma unroll
-                for (int cb = 0; cb < 4; ++cb)
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) L.U[(16 * ib + 4 * r + kg) * US + 16 * cb + li] = acc[ib][cb][r];
-            lds_order();
+                        for (int r = 0; r < 4; ++r) L.U[16 * ib + 4 * r + kg] = acc[ib][N2 >> 4][r];
+                }
+                lds_order();
+            }
             // mode terms on lanes < F: gradient, Hessian diagonal and potential
             R vc = 0;
             if (modeLane) {
                 R sm;
                 if constexpr (SM_MFMA) {
-                    sm = (R)L.U[lane * US + N2];
+                    sm = (R)L.U[lane];
                 } else {
                     sm = 0;
 #pragma unroll
@@ -472,14 +505,27 @@ traj_big_kernel(TrajArgs A, const ProblemDev *__restrict__ P0)
             }
             S.add(-hk * (double)wave_sum32(vc));
             lds_order();
-            // tangent kick of every column: dp -= hk (h o dq + 4 q o W)
-            if (colLane) {
+            // tangent kick of every column: dp -= hk (h o dq + 4 q o W), the rows
+            // of W in this lane's column four at a time: after the transpose
+            // w[c] is row 16 ib + 4 r + c
 #pragma unroll
-                for (int i = 0; i < F; ++i) {
-                    const double2 g = qh[i];
-                    dp[i] = fma(-hk, fma(g.y, dq[i], g.x * L.U[i * US + lane]), dp[i]);
+            for (int ib = 0; ib < 2; ++ib)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    if (16 * ib + 4 * r >= F) continue;
+                    double w[4] = {acc[ib][0][r], acc[ib][1][r], acc[ib][2][r], acc[ib][3][r]};
+                    group_transpose(w);
+                    if (colLane) {
+#pragma unroll
+                        for (int c = 0; c < 4; ++c) {
+                            const int i = 16 * ib + 4 * r + c;
+                            if (i < F) {
+                                const double2 g = qh[i];
+                                dp[i] = fma(-hk, fma(g.y, dq[i], g.x * w[c]), dp[i]);
+                            }
+                        }
+                    }
                 }
-            }
             lds_order();
         }
 
