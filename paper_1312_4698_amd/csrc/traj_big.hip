@@ -110,47 +110,45 @@ __device__ __attribute__((always_inline)) inline T wave_sum32(T v)
         return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 31));
 }
 
-// Lane of the live row at position ppos (exactly one).
-__device__ __attribute__((always_inline)) inline int pivot_lane(bool alive, int pos, int ppos)
-{
-    const unsigned long long m = __ballot(alive && pos == ppos);
-    return __builtin_ctzll(m);
-}
-
-// det of the real N x N matrix whose row `pos` lives in a[] of the lanes with
-// `active` set (positions 0..N-1, one row per lane of the wave).  The pivot of
-// each column is the live row with the largest |a_k| (compared as 32-bit keys,
-// ties to the lowest position), found by a wave-wide maximum; its row is
-// read into scalar registers lane by lane, so the elimination needs no LDS.
-// The row at position k and the pivot swap positions; the determinant
-// changes sign when they differ.  Every lane returns det.
+// det of the real N x N matrix whose row r lives in a[] of lane r (`active`
+// on lanes 0..N-1; rows stay in place).  The pivot of each column is the live
+// row with the largest |a_k|, compared as 32-bit keys (the magnitude's high
+// word with the row's tag 63 - r in its low six bits, so ties go to the lowest
+// row) by a wave-wide maximum, which names the pivot lane directly; the pivot
+// row is read into scalar registers lane by lane, so the elimination needs no
+// LDS.  The determinant is the product of the pivots times the sign of the
+// pivot order r_0, r_1, ..., whose inversions are the live rows below each
+// r_k (a popcount of the wave-uniform set of rows not yet used).  Every lane
+// returns det.
 template <int N>
-__device__ __attribute__((always_inline)) inline double lu_det_rows(double (&a)[N], bool active, int pos)
+__device__ __attribute__((always_inline)) inline double lu_det_rows(double (&a)[N], bool active)
 {
+    const int lane = threadIdx.x;
     bool alive = active;
+    unsigned long long live = __ballot(active);
+    unsigned inversions = 0;
     double det = 1.0;
     // lookahead: column k + 1 is updated first and its pivot search runs
     // while the rest of the row is eliminated
-    unsigned win = wave_max_u32(alive ? pivot_key32(fabs(a[0]), pos) : 0u);
+    unsigned win = wave_max_u32(alive ? pivot_key32(fabs(a[0]), lane) : 0u);
 #pragma unroll
     for (int k = 0; k < N; ++k) {
-        const int ppos = 63 - (int)(win & 63u);
-        const int pl = pivot_lane(alive, pos, ppos);
-        const bool isp = alive && pos == ppos;
+        const int pl = 63 - (int)(win & 63u);
         const double pk = readlane_f64(a[k], pl);
-        det *= (ppos != k) ? -pk : pk;
+        det *= pk;
         // the product is taken here, in a vector register: left to the
         // scheduler, the 2N pivot halves stay live in scalar registers until
         // the end and push the kernel into scalar spills
         asm volatile("" : "+v"(det));
-        pos = (alive && pos == k) ? ppos : pos;
-        alive = alive && !isp;
+        inversions += __builtin_popcountll(live & ((1ull << pl) - 1ull));
+        live &= ~(1ull << pl);
+        alive = alive && lane != pl;
         if (k + 1 < N) {
             // rows out of play (used pivots, lanes beyond N) are updated too:
             // their keys are masked, so their values are never read again
             const double l = a[k] * rcp_nr(pk);
             a[k + 1] = fma(-l, readlane_f64(a[k + 1], pl), a[k + 1]);
-            win = wave_max_u32(alive ? pivot_key32(fabs(a[k + 1]), pos) : 0u);
+            win = wave_max_u32(alive ? pivot_key32(fabs(a[k + 1]), lane) : 0u);
             // the pivot row arrives four entries at a time, so several
             // readlanes are in flight before their scalar registers are used
 #pragma unroll
@@ -165,7 +163,7 @@ __device__ __attribute__((always_inline)) inline double lu_det_rows(double (&a)[
             }
         }
     }
-    return det;
+    return (inversions & 1u) ? -det : det;
 }
 
 // 4 x 4 transpose between the wave's four row groups of 16 lanes and four
@@ -210,35 +208,37 @@ __device__ __attribute__((always_inline)) inline void half_pair(double v, double
     upper = __hiloint2double(b[1], a[1]);
 }
 
-// det of the complex N x N matrix (N <= 32) whose row `pos` has its real
-// parts in x[] of lane pos and its imaginary parts in x[] of lane pos + 32
-// (`active` on both lanes of rows 0..N-1; `imag` on the upper half).  Pivot
-// on |a_k|^2 (keys from the real-part lanes), otherwise as lu_det_rows.  Each
-// lane updates one part, so every entry costs the pivot row's four readlanes
-// and two FMAs per lane; a whole complex row per lane would take four FMAs
-// and leave the upper half of the wave idle.  Every lane returns det.
+// det of the complex N x N matrix (N <= 32) whose row r has its real parts in
+// x[] of lane r and its imaginary parts in x[] of lane r + 32 (`active` on
+// both lanes of rows 0..N-1; `imag` on the upper half).  Pivot on |a_k|^2
+// (keys from the real-part lanes), otherwise as lu_det_rows.  Each lane
+// updates one part, so every entry costs the pivot row's four readlanes and
+// two FMAs per lane; a whole complex row per lane would take four FMAs and
+// leave the upper half of the wave idle.  Every lane returns det.
 template <int N>
-__device__ __attribute__((always_inline)) inline void lu_det_rows_complex_split(double (&x)[N], bool active, int pos,
-                                                                                bool imag, double &dr, double &di)
+__device__ __attribute__((always_inline)) inline void lu_det_rows_complex_split(double (&x)[N], bool active, bool imag,
+                                                                                double &dr, double &di)
 {
+    const int row = threadIdx.x & 31;
     bool alive = active;
+    unsigned live = (unsigned)__ballot(active && !imag);
+    unsigned inversions = 0;
     double zr = 1.0, zi = 0.0;
     double re, im;  // this row's entry in the column being eliminated
     half_pair(x[0], re, im);
-    unsigned win = wave_max_u32((alive && !imag) ? pivot_key32(fma(re, re, im * im), pos) : 0u);
+    unsigned win = wave_max_u32((alive && !imag) ? pivot_key32(fma(re, re, im * im), row) : 0u);
 #pragma unroll
     for (int k = 0; k < N; ++k) {
-        const int ppos = 63 - (int)(win & 63u);
-        const int pl = pivot_lane(alive && !imag, pos, ppos);  // the pivot row's real-part lane
-        const bool isp = alive && pos == ppos;
+        const int pl = 63 - (int)(win & 63u);  // the pivot row's real-part lane
         const double pr = readlane_f64(x[k], pl), pi = readlane_f64(x[k], pl + 32);
         const double nr = zr * pr - zi * pi;
         const double ni = zr * pi + zi * pr;
-        zr = (ppos != k) ? -nr : nr;
-        zi = (ppos != k) ? -ni : ni;
+        zr = nr;
+        zi = ni;
         asm volatile("" : "+v"(zr), "+v"(zi));  // as in lu_det_rows
-        pos = (alive && pos == k) ? ppos : pos;
-        alive = alive && !isp;
+        inversions += __builtin_popcount(live & ((1u << pl) - 1u));
+        live &= ~(1u << pl);
+        alive = alive && row != pl;
         if (k + 1 < N) {
             const double inv = rcp_nr(fma(pr, pr, pi * pi));
             const double lr = (re * pr + im * pi) * inv;  // rows out of play: as in lu_det_rows
@@ -252,7 +252,7 @@ __device__ __attribute__((always_inline)) inline void lu_det_rows_complex_split(
                 x[k + 1] = fma(-u, br, fma(v, bi, x[k + 1]));
             }
             half_pair(x[k + 1], re, im);
-            win = wave_max_u32((alive && !imag) ? pivot_key32(fma(re, re, im * im), pos) : 0u);
+            win = wave_max_u32((alive && !imag) ? pivot_key32(fma(re, re, im * im), row) : 0u);
 #pragma unroll
             for (int j0 = k + 2; j0 < N; j0 += 2) {
                 double br[2], bi[2];
@@ -268,8 +268,8 @@ __device__ __attribute__((always_inline)) inline void lu_det_rows_complex_split(
             }
         }
     }
-    dr = zr;
-    di = zi;
+    dr = (inversions & 1u) ? -zr : zr;
+    di = (inversions & 1u) ? -zi : zi;
 }
 
 template <int F, bool MIXED>
@@ -559,7 +559,7 @@ traj_big_kernel(TrajArgs A, const ProblemDev *__restrict__ P0)
                 const double u = L.T[(F + i) * RS + colU], v = L.T[i * RS + colV];
                 x[i] = 0.5 * (si * u * alphaA + v * isi * betaA);
             }
-            lu_det_rows_complex_split<F>(x, rowLane, rc, imagLane, dAr, dAi);
+            lu_det_rows_complex_split<F>(x, rowLane, imagLane, dAr, dAi);
         }
 
         // stability monitor |det(M)^2 - 1| on checked steps
@@ -571,7 +571,7 @@ traj_big_kernel(TrajArgs A, const ProblemDev *__restrict__ P0)
                 a[i] = dp[i];
                 a[F + i] = dq[i];
             }
-            const double dM = lu_det_rows<N2>(a, colLane, lane);
+            const double dM = lu_det_rows<N2>(a, colLane);
             const double dev = fabs(dM * dM - 1.0);
             detM = dM;
             if (!(dev <= maxdev)) maxdev = dev;
