@@ -185,10 +185,11 @@ def _energy_reader():
         return None
 
 
-def run_form(scivr, torch, prob, n, steps, warmup, seed0=1000, chunk=0, energy=None):
+def run_form(scivr, torch, prob, n, steps, warmup, seed0=1000, chunk=0, energy=None, stop_flagged=False):
     """Time `steps` whole passes (sample + propagate + accumulate) of one form."""
     stream = torch.cuda.current_stream()
     ctx = scivr.Context(prob, max_traj=n)
+    ctx.set_stop_flagged(stop_flagged)
 
     def one_step(i):
         ctx.sample_husimi(seed=seed0 + i, n_traj=n, stream=stream)
@@ -660,6 +661,9 @@ def main():
     ap.add_argument("--learned", type=int, default=1, help="run the learned-proposal study (1) or not (0)")
     ap.add_argument("--fft", type=int, default=1,
                     help="also time the exact FFT-autocorrelation Fourier step against the GEMM (1) or not (0)")
+    ap.add_argument("--stop-flagged", type=int, default=0,
+                    help="stop trajectories at the step the stability monitor flags them (F > 16 kernel); "
+                         "the value then still counts every trajectory-step of the batch")
     ap.add_argument("--chunk", type=int, default=0,
                     help="propagate in calls of this many time steps, printing progress (0: one call)")
     ap.add_argument("--cpu-single", type=int, default=64,
@@ -714,11 +718,13 @@ def main():
     print(f"[bench] {args.workload}: F={prob.F} n={n} steps={prob.n_steps} K={prob.n_energies}", file=sys.stderr,
           flush=True)
     energy = _energy_reader()
-    main_run = run_form(scivr, torch, prob, n, args.steps, args.warmup, chunk=args.chunk, energy=energy)
+    main_run = run_form(scivr, torch, prob, n, args.steps, args.warmup, chunk=args.chunk, energy=energy,
+                        stop_flagged=bool(args.stop_flagged))
     plain = None
     if args.plain:
         pprob, _ = inputs.workload(args.plain)
-        plain = run_form(scivr, torch, pprob, n, args.steps, args.warmup, chunk=args.chunk, energy=energy)
+        plain = run_form(scivr, torch, pprob, n, args.steps, args.warmup, chunk=args.chunk, energy=energy,
+                         stop_flagged=bool(args.stop_flagged))
 
     wall = main_run["wall"]
     kt = main_run["kt"]
@@ -788,6 +794,9 @@ def main():
                      + ("the dense FP16 MFMA peak / 3" if mixed else "the FP64 MFMA peak"),
         },
         "n_good_fraction": main_run["n_good"] / max(main_run["n_total"], 1),
+        "stop_flagged": bool(args.stop_flagged) and {
+            "note": "flagged trajectories stopped at their flag (F > 16 kernel): value and the roofline count every "
+                    "trajectory-step of the batch, so they are the time-to-spectrum rate, not the kernel's"},
         "energy": _energy_summary(main_run, args.steps),
         "cpu_baseline": None,
     }

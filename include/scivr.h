@@ -147,6 +147,22 @@ scivr_status scivr_set_initial(scivr_ctx *ctx, int64_t n_traj, const double *p0,
 scivr_status scivr_propagate(scivr_ctx *ctx, int32_t step_begin, int32_t step_end, void *stream);
 
 /*
+ * Stop integrating a trajectory at the step where the stability monitor flags
+ * it (enable != 0), as the sequential code of the paper's implementation
+ * section interrupts such a trajectory, instead of running it to T as its GPU
+ * design does.  A flagged trajectory contributes nothing to the estimate, so
+ * the spectra, the good counts and the contributions are those of the full
+ * run, bit for bit; its amplitudes after the flag stay zero.  What changes is
+ * scivr_read_state for flagged trajectories: their p, q, S, phi, M and the
+ * largest |det(M)^2 - 1| are those of the step at which they were flagged.
+ * It takes effect in the kernel for F > 16, where one wave holds one
+ * trajectory and stopping it costs no divergence; for F <= 16 (several
+ * trajectories per wave) the setting is kept and has no effect.  Off by
+ * default; applies to later scivr_propagate calls.
+ */
+scivr_status scivr_set_stop_flagged(scivr_ctx *ctx, int32_t enable);
+
+/*
  * After all n_steps are done: the Fourier sums A_jk = sum_c amp_jc e^{i E_k c dt}
  * of the batch, and ADD sum_j good_j w_j |A_jk|^2 and the batch's n_good
  * and n_traj into the context's running totals (so several batches form one

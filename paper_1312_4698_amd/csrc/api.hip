@@ -444,12 +444,20 @@ scivr_status scivr_propagate(scivr_ctx *ctx, int32_t step_begin, int32_t step_en
     a.n_steps = ctx->n_steps;
     a.check_every = ctx->check_every;
     a.n_refs = ctx->n_refs;
+    a.stop_flagged = ctx->stop_flagged;
     Timed tm(ctx, s, 1);
     HIPCALL(ctx, launch_traj(ctx->F, ctx->precision == SCIVR_PRECISION_MIXED, a, s));
     tm.done();
     ctx->steps_done = step_end;
     ctx->accumulated = false;
     ctx->full_valid = false;
+    return SCIVR_OK;
+}
+
+scivr_status scivr_set_stop_flagged(scivr_ctx *ctx, int32_t enable)
+{
+    CHECK_CTX(ctx);
+    ctx->stop_flagged = enable != 0;
     return SCIVR_OK;
 }
 

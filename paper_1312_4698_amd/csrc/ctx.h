@@ -37,6 +37,7 @@ struct scivr_ctx {
     double *d_goodw = nullptr;      // running sum of good_j r_j (r_j = Husimi / sampling density)
     double *d_goodw_row = nullptr;  // good_j r_j of the current batch [npad]
     bool husimi_batch = false;      // the batch was drawn by the Husimi sampler (r_j = 1 exactly)
+    int32_t stop_flagged = 0;       // scivr_set_stop_flagged
     int32_t n_refs = 1;             // reference states of the spectra (d_amp [t][ref][npad], d_total [ref][K])
 
     int64_t n_traj = 0;      // current batch size

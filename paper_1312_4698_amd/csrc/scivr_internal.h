@@ -55,6 +55,7 @@ struct TrajArgs {
     int64_t n, npad;
     int32_t step_begin, step_end, n_steps, check_every;
     int32_t n_refs;         // FP64 form: amplitudes for each reference state
+    int32_t stop_flagged;   // stop a trajectory once flagged (F > 16 kernel)
 };
 
 // Time samples per FP16 MFMA k-step of the mixed-form Fourier GEMM.

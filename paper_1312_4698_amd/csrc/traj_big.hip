@@ -412,6 +412,16 @@ traj_big_kernel(TrajArgs A, const ProblemDev *__restrict__ P0)
         }
     };
 
+    auto store_zero = [&](int t) {
+        if constexpr (!MIXED) {
+            for (int m = 0; m < A.n_refs; ++m) A.amp[((int64_t)t * A.n_refs + m) * NP + jr] = make_double2(0.0, 0.0);
+        } else {
+            const int64_t e = ((int64_t)(t >> 3) * NP + jr) * 8 + (t & 7);
+#pragma unroll
+            for (int pl = 0; pl < 4; ++pl) A.amp16[pl * A.plane + e] = (_Float16)0.0f;
+        }
+    };
+
     if (A.step_begin == 0) {
         double ph0;
         const double ex0 = overlap(P, 0, ph0);
@@ -421,6 +431,13 @@ traj_big_kernel(TrajArgs A, const ProblemDev *__restrict__ P0)
 
     for (int step = A.step_begin; step < A.step_end; ++step) {
         ConstProblem Ps = opaque(P0);
+        // a flagged trajectory contributes nothing: when asked, it stops here
+        // (its amplitudes stay zero; lane 0's flag also covers a non-finite
+        // phase or action)
+        if (A.stop_flagged && !__builtin_amdgcn_readfirstlane((int)good)) {
+            if (lane == 0) store_zero(step + 1);
+            continue;
+        }
 #pragma unroll 1
         for (int s = 0; s < 4; ++s) {
             ConstProblem Pk = opaque(P0);

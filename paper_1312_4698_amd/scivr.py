@@ -38,7 +38,7 @@ _STATUS = {EINVAL: "SCIVR_EINVAL", ENOMEM: "SCIVR_ENOMEM", EDEVICE: "SCIVR_EDEVI
 # Every symbol the header declares.
 EXPORTED = (
     "scivr_abi_version", "scivr_create", "scivr_destroy", "scivr_last_error", "scivr_sample_husimi",
-    "scivr_set_initial", "scivr_propagate", "scivr_accumulate_spectrum", "scivr_accumulate_spectrum_fft",
+    "scivr_set_initial", "scivr_propagate", "scivr_set_stop_flagged", "scivr_accumulate_spectrum", "scivr_accumulate_spectrum_fft",
     "scivr_accumulate_spectrum_fft_noalloc", "scivr_accumulate_spectrum_full", "scivr_read_lags",
     "scivr_read_spectrum", "scivr_read_totals", "scivr_set_references", "scivr_read_spectrum_ref",
     "scivr_reset_spectrum", "scivr_batch_info", "scivr_read_initial", "scivr_read_state",
@@ -107,6 +107,7 @@ def load() -> ctypes.CDLL:
         "scivr_read_spectrum": (i32, [v, v, ctypes.POINTER(i64), ctypes.POINTER(i64)]),
         "scivr_read_spectrum_ref": (i32, [v, i32, v, ctypes.POINTER(i64), ctypes.POINTER(i64)]),
         "scivr_set_references": (i32, [v, i32, v, v]),
+        "scivr_set_stop_flagged": (i32, [v, i32]),
         "scivr_reset_spectrum": (i32, [v, v]),
         "scivr_batch_info": (i32, [v, ctypes.POINTER(i64), ctypes.POINTER(i32)]),
         "scivr_read_initial": (i32, [v, v, v, v]),
@@ -264,6 +265,10 @@ class Context:
             st = self._lib.scivr_read_spectrum_ref(self._h, int(ref), _np_ptr(I), ctypes.byref(ng), ctypes.byref(nt))
         self._check(st, allow=(ENOGOOD,))
         return I, int(ng.value), int(nt.value)
+
+    def set_stop_flagged(self, enable: bool = True):
+        """Stop integrating trajectories once the stability monitor flags them (F > 16)."""
+        self._check(self._lib.scivr_set_stop_flagged(self._h, 1 if enable else 0))
 
     def set_references(self, p_eq, q_eq):
         """Further reference states [n_extra][F] of the problem's widths, fed by every later batch."""

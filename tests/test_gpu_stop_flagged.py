@@ -1,0 +1,83 @@
+"""scivr_set_stop_flagged: trajectories stop at the step the stability
+monitor flags them (the paper's sequential code interrupts them; its GPU
+design runs them to T).  A flagged trajectory contributes nothing, so the
+spectrum, the good count and the contributions must equal the full run's bit
+for bit; good trajectories' final states too.  A flagged trajectory's state is
+the one at its flag, so its largest |det(M)^2 - 1| cannot exceed the full
+run's.  The threshold is set to the median of each batch's own monitor
+values, so about half of the trajectories are flagged part-way."""
+import sys
+import time
+
+import numpy as np
+import pytest
+
+from paper_1312_4698_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def scivr():
+    from paper_1312_4698_amd import scivr as S
+    S.load()
+    return S
+
+
+def _run(S, prob, n, stop, chunks=None):
+    ctx = S.Context(prob, max_traj=n)
+    ctx.set_stop_flagged(stop)
+    ctx.sample_husimi(21, n)
+    t = time.time()
+    b = 0
+    for e in (chunks or []) + [prob.n_steps]:
+        ctx.propagate(b, e)
+        b = e
+    ctx.accumulate()
+    I, ng, nt = ctx.read_spectrum()
+    wall = time.time() - t
+    out = dict(I=I, ng=ng, c=ctx.read_contributions(), st=ctx.read_state(), wall=wall)
+    ctx.close()
+    return out
+
+
+@pytest.mark.parametrize("F,precision,n,ns", [
+    (17, inputs.PRECISION_FP64, 40, 200),
+    (30, inputs.PRECISION_FP64, 32, 160),
+    (30, inputs.PRECISION_MIXED, 32, 160),
+    (9, inputs.PRECISION_FP64, 70, 200),  # several trajectories per wave: kept, no effect
+])
+def test_stop_flagged_keeps_the_estimate(scivr, F, precision, n, ns):
+    base = inputs.morse_quartic(F, F, n_steps=ns, n_energies=128, e_max=0.2 if F > 9 else 0.1)
+    base = base.replace(precision=precision)
+    probe = _run(scivr, base, n, False)
+    tol = float(np.median(probe["st"]["maxdev"]))
+    prob = base.replace(det_tol=tol)
+    full = _run(scivr, prob, n, False)
+    stop = _run(scivr, prob, n, True)
+    chunked = _run(scivr, prob, n, True, chunks=[1, ns // 3])
+    good = full["st"]["good"] == 1
+    _say(f"[stop] F={F} {'mixed' if precision else 'fp64'}: tol {tol:.2e}, {int((~good).sum())} of {n} flagged, "
+         f"wall {full['wall']:.3f} s full, {stop['wall']:.3f} s stopped")
+    assert 0 < good.sum() < n
+    for r in (stop, chunked):
+        assert r["ng"] == full["ng"]
+        assert np.array_equal(r["I"], full["I"])
+        assert np.array_equal(r["c"], full["c"])
+        assert np.array_equal(r["st"]["good"], full["st"]["good"])
+        for k in ("p", "q", "S", "phi", "detM", "maxdev"):  # p, q are [F][n]
+            assert np.array_equal(r["st"][k][..., good], full["st"][k][..., good]), k
+        assert np.array_equal(r["st"]["M"][good], full["st"]["M"][good])
+        assert np.all(r["st"]["maxdev"][~good] <= full["st"]["maxdev"][~good])
+        assert np.all(r["st"]["maxdev"][~good] > tol)
+    # the chunked run stops at the same steps as the single launch
+    for k in ("p", "q", "S", "phi", "maxdev"):
+        assert np.array_equal(chunked["st"][k], stop["st"][k]), k
+    if F <= 16:  # no effect in the small-F kernel
+        for k in ("p", "q", "S", "phi", "maxdev"):
+            assert np.array_equal(stop["st"][k], full["st"][k]), k
