@@ -426,7 +426,7 @@ def _jackknife_peaks(peaks, E, T, tots, Gs, scale, ref, tol):
 
 
 def c5_study(scivr, torch, inputs, peaks, n, B=8, seed=303, n_train=32768, layers=4, width=256, epochs=10,
-             batch=4096, lr=1e-3, chunk=2048, frac=0.2, min_ess=0.05, variants=((1.0, 0.1), (0.0, 0.1))):
+             batch=4096, lr=1e-3, chunk=2048, frac=0.2, min_ess=0.05, variants=((1.0, 0.1), (0.0, 0.1)), stop_flagged=True):
     """The F=30 configuration: mixed form + learned proposal against the plain
     FP64 GPU judge, with Monte Carlo error bars.
 
@@ -440,6 +440,12 @@ def c5_study(scivr, torch, inputs, peaks, n, B=8, seed=303, n_train=32768, layer
     Peaks are those of the judge with I >= frac * max (and >= 5 % for the
     full list), matched within 20 cm^-1; each carries the jackknife standard
     error over the B batches."""
+    def _ctx(prob, max_traj):
+        # flagged trajectories stop at their flag: the estimates are bit-identical
+        c = scivr.Context(prob, max_traj=max_traj)
+        c.set_stop_flagged(stop_flagged)
+        return c
+
     CM = inputs.CM1_PER_HARTREE
     pf, _ = inputs.workload("F30_fp64")
     pm, _ = inputs.workload("F30_mixed")
@@ -455,7 +461,7 @@ def c5_study(scivr, torch, inputs, peaks, n, B=8, seed=303, n_train=32768, layer
         print(f"[c5] {label} done", file=sys.stderr, flush=True)
 
     def batched(prob, fill, label):
-        ctx = scivr.Context(prob, max_traj=nb)
+        ctx = _ctx(prob, max_traj=nb)
         tots, Gs, goods, pts = [], [], [], []
         for b in range(B):
             ctx.reset_spectrum()
@@ -485,7 +491,7 @@ def c5_study(scivr, torch, inputs, peaks, n, B=8, seed=303, n_train=32768, layer
     both = [jg & mg for jg, mg in zip(jgood, mgood)]
     sub = {}
     for form, prob in (("fp64", pf), ("mixed", pm)):
-        ctx = scivr.Context(prob, max_traj=max(1, max(int(x.sum()) for x in both)))
+        ctx = _ctx(prob, max_traj=max(1, max(int(x.sum()) for x in both)))
         tots, Gs = [], []
         for b in range(B):
             keep = np.flatnonzero(both[b])
@@ -515,7 +521,7 @@ def c5_study(scivr, torch, inputs, peaks, n, B=8, seed=303, n_train=32768, layer
     # indicator (temper 0), which asks for the region where trajectories stay
     # good with equal weight.
     t0 = time.perf_counter()
-    ctx = scivr.Context(pm, max_traj=max(nb, n_train))
+    ctx = _ctx(pm, max_traj=max(nb, n_train))
     ctx.sample_husimi(seed=seed + 1, n_traj=n_train, first_index=1 << 40)
     propagate(ctx, pm, "training batch")
     ctx.accumulate()
@@ -628,7 +634,7 @@ def c5_study(scivr, torch, inputs, peaks, n, B=8, seed=303, n_train=32768, layer
         "learned": learned,
         "flow": {"width": width, "layers": layers, "n_train": n_train, "epochs": epochs,
                  "min_ess_frac": min_ess, "training_batch_s": t_batch},
-        "wall_s": {"judge": t_judge, "mixed": t_mixed},
+        "wall_s": {"judge": t_judge, "mixed": t_mixed}, "stop_flagged": stop_flagged,
     }
     for key in ("precision_identical_subset", "mixed_vs_judge"):
         out[key]["worst_abs_delta_cm1"] = worst(out[key]["peaks"])
@@ -673,6 +679,8 @@ def main():
     ap.add_argument("--c5-variants", default="1:0.1,0:0.1",
                     help="learned-proposal variants of the F=30 study, temper:alpha pairs (temper 0: good indicator)")
     ap.add_argument("--c5-train", type=int, default=32768, help="training batch of the F=30 study's flows")
+    ap.add_argument("--c5-stop-flagged", type=int, default=1,
+                    help="stop flagged trajectories in the F=30 study (bit-identical estimates, shorter runs)")
     ap.add_argument("--oracle-full", default="",
                     help="only time the oracle over this whole workload on the host cores and exit")
     ap.add_argument("--sweep", default="",
@@ -705,7 +713,8 @@ def main():
         return
     if args.c5:
         vs = tuple(tuple(float(x) for x in v.split(":")) for v in args.c5_variants.split(","))
-        res = c5_study(scivr, torch, inputs, peaks, args.c5, n_train=args.c5_train, variants=vs)
+        res = c5_study(scivr, torch, inputs, peaks, args.c5, n_train=args.c5_train, variants=vs,
+                       stop_flagged=bool(args.c5_stop_flagged))
         print(json.dumps({"c5_study": res}))
         return
     if args.sweep:
