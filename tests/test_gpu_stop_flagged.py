@@ -81,3 +81,39 @@ def test_stop_flagged_keeps_the_estimate(scivr, F, precision, n, ns):
     if F <= 16:  # no effect in the small-F kernel
         for k in ("p", "q", "S", "phi", "maxdev"):
             assert np.array_equal(stop["st"][k], full["st"][k]), k
+
+
+def test_stop_flagged_with_references_and_fft(scivr):
+    """Several reference states and the FFT form of the Fourier step see the
+    same amplitudes with and without stopping (zeros after each flag)."""
+    F, n, ns = 17, 40, 200
+    base = inputs.morse_quartic(F, F, n_steps=ns, n_energies=96, e_max=0.2)
+    probe = _run(scivr, base, n, False)
+    prob = base.replace(det_tol=float(np.median(probe["st"]["maxdev"])))
+    rng = np.random.default_rng(5)
+    pe = rng.uniform(-0.5, 0.5, (2, F)) * np.sqrt(prob.gamma)
+    qe = rng.uniform(-0.5, 0.5, (2, F)) / np.sqrt(prob.gamma)
+    out = {}
+    for stop in (False, True):
+        ctx = scivr.Context(prob, max_traj=n)
+        ctx.set_stop_flagged(stop)
+        ctx.set_references(pe, qe)
+        ctx.sample_husimi(4, n)
+        ctx.propagate()
+        ctx.accumulate()
+        refs = [ctx.read_spectrum(m) for m in range(3)]
+        ctx.close()
+        cf = scivr.Context(prob, max_traj=n)
+        cf.set_stop_flagged(stop)
+        cf.sample_husimi(4, n)
+        cf.propagate()
+        cf.accumulate_fft()
+        fft = cf.read_spectrum()
+        cf.close()
+        out[stop] = (refs, fft)
+    _say(f"[stop] references and FFT form: {n - out[False][1][1]} of {n} flagged")
+    for m in range(3):
+        assert np.array_equal(out[True][0][m][0], out[False][0][m][0]), m
+        assert out[True][0][m][1] == out[False][0][m][1]
+    assert np.array_equal(out[True][1][0], out[False][1][0])
+    assert out[True][1][1] == out[False][1][1] < n
