@@ -248,7 +248,7 @@ scivr_status scivr_create(const scivr_problem *p, int32_t device, scivr_ctx **ou
     c->npad = round_up(p->max_traj, GEMM_BM);
     c->nt = p->n_steps + 1;
     c->nt_pad = (int32_t)round_up(c->nt, GEMM_BK);
-    c->nt_alloc = c->nt_pad + GEMM_BK;
+    c->nt_alloc = c->nt_pad + 2 * GEMM_BK;  // the FP64 GEMM prefetches two time blocks ahead
     c->kpad = (int32_t)round_up(p->n_energies, GEMM_BN);
     c->nt16 = (int32_t)round_up(c->nt, GEMM16_BK);
     c->row_tiles = (int32_t)(c->npad / GEMM_BM);

@@ -14,9 +14,11 @@
 // (Cr += Ar Br - Ai Bi, Ci += Ar Bi + Ai Br).  Both operands are time-major, so
 // each MFMA operand fragment (16 consecutive trajectories or energies at one
 // time sample per lane quarter) is a coalesced 256-byte load straight into
-// registers; the next time block is prefetched while the current one is
-// multiplied.  A workgroup of four waves covers 128 trajectories x 128
-// energies (2 x 2 waves of 64 x 64); |A|^2 never leaves registers: the epilogue
+// registers; the time block after next is prefetched while the current one
+// is multiplied.  A workgroup of eight waves covers 128 trajectories x 128
+// energies (2 x 4 waves of 64 x 32, two waves per SIMD: each wave's 128
+// accumulator registers fit beside its operands, so the accumulators are not
+// shuffled between register files); |A|^2 never leaves registers: the epilogue
 // reduces it over trajectories (weighted, for the spectrum) and over energies
 // (for the per-trajectory contributions).  Workgroups are mapped so that each
 // of the eight XCDs walks a contiguous range of trajectory tiles with the
@@ -29,7 +31,7 @@ namespace {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 
-__global__ void __launch_bounds__(256, 1) fourier_fp64_kernel(GemmArgs G)
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2))) fourier_fp64_kernel(GemmArgs G)
 {
     const int wg = blockIdx.x;
     const int nwg = G.row_tiles * G.col_tiles;
@@ -43,20 +45,21 @@ __global__ void __launch_bounds__(256, 1) fourier_fp64_kernel(GemmArgs G)
         rt = wg / G.col_tiles;
         ct = wg % G.col_tiles;
     }
+    // eight waves: 2 x 4 of 64 trajectories x 32 energies
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int wr = wave >> 1, wc = wave & 1;
+    const int wr = wave >> 2, wc = wave & 3;
     // row tile rt is tile rt % tiles_per_ref of reference state rt / tiles_per_ref
     const int ref = rt / G.tiles_per_ref;
     const int64_t lrow0 = (int64_t)(rt - ref * G.tiles_per_ref) * GEMM_BM + wr * 64;  // trajectory of the tile's row
     const int64_t row0 = ref * G.ref_rows + lrow0;
-    const int col0 = ct * GEMM_BN + wc * 64;
+    const int col0 = ct * GEMM_BN + wc * 32;
     const int kk = lane >> 4, ii = lane & 15;
 
-    d4 cr[4][4], ci[4][4];
+    d4 cr[4][2], ci[4][2];
 #pragma unroll
     for (int bi = 0; bi < 4; ++bi)
 #pragma unroll
-        for (int bj = 0; bj < 4; ++bj) {
+        for (int bj = 0; bj < 2; ++bj) {
             cr[bi][bj] = (d4){0.0, 0.0, 0.0, 0.0};
             ci[bi][bj] = (d4){0.0, 0.0, 0.0, 0.0};
         }
@@ -66,51 +69,64 @@ __global__ void __launch_bounds__(256, 1) fourier_fp64_kernel(GemmArgs G)
     const int64_t astep = (int64_t)GEMM_BK * G.npad;
     const int64_t bstep = (int64_t)GEMM_BK * G.kpad;
 
-    double2 a[4], b[4];
+    // operands of the current time block (a, b), the next (an, bn) and the one
+    // after (loaded while the current one is multiplied).  The buffers hold
+    // two zero time blocks beyond nt_pad, so the prefetch never leaves them.
+    double2 a[4], b[2], an[4], bn[2];
 #pragma unroll
     for (int x = 0; x < 4; ++x) {
         a[x] = Ap[x * 16];
-        b[x] = Bp[x * 16];
+        an[x] = Ap[astep + x * 16];
     }
-    // the buffers hold one zero time block beyond nt_pad, so the prefetch never leaves them
+#pragma unroll
+    for (int x = 0; x < 2; ++x) {
+        b[x] = Bp[x * 16];
+        bn[x] = Bp[bstep + x * 16];
+    }
+    Ap += astep;
+    Bp += bstep;
     for (int t0 = 0; t0 < G.nt_pad; t0 += GEMM_BK) {
         Ap += astep;
         Bp += bstep;
-        double2 an[4], bn[4];
+        double2 a2[4], b2[2];
 #pragma unroll
-        for (int x = 0; x < 4; ++x) {
-            an[x] = Ap[x * 16];
-            bn[x] = Bp[x * 16];
-        }
-        // the four real products in four sweeps over the 16 blocks, so that the
-        // two updates of one accumulator are 16 independent MFMAs apart
+        for (int x = 0; x < 4; ++x) a2[x] = Ap[x * 16];
+#pragma unroll
+        for (int x = 0; x < 2; ++x) b2[x] = Bp[x * 16];
+        // the four real products in four sweeps over the 8 blocks, so that the
+        // two updates of one accumulator are 8 independent MFMAs apart
         double nai[4];
 #pragma unroll
         for (int bi = 0; bi < 4; ++bi) nai[bi] = -a[bi].y;
 #pragma unroll
         for (int bi = 0; bi < 4; ++bi)
 #pragma unroll
-            for (int bj = 0; bj < 4; ++bj)
+            for (int bj = 0; bj < 2; ++bj)
                 cr[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[bi].x, b[bj].x, cr[bi][bj], 0, 0, 0);
 #pragma unroll
         for (int bi = 0; bi < 4; ++bi)
 #pragma unroll
-            for (int bj = 0; bj < 4; ++bj)
+            for (int bj = 0; bj < 2; ++bj)
                 ci[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[bi].x, b[bj].y, ci[bi][bj], 0, 0, 0);
 #pragma unroll
         for (int bi = 0; bi < 4; ++bi)
 #pragma unroll
-            for (int bj = 0; bj < 4; ++bj)
+            for (int bj = 0; bj < 2; ++bj)
                 cr[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(nai[bi], b[bj].y, cr[bi][bj], 0, 0, 0);
 #pragma unroll
         for (int bi = 0; bi < 4; ++bi)
 #pragma unroll
-            for (int bj = 0; bj < 4; ++bj)
+            for (int bj = 0; bj < 2; ++bj)
                 ci[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[bi].y, b[bj].x, ci[bi][bj], 0, 0, 0);
 #pragma unroll
         for (int x = 0; x < 4; ++x) {
             a[x] = an[x];
+            an[x] = a2[x];
+        }
+#pragma unroll
+        for (int x = 0; x < 2; ++x) {
             b[x] = bn[x];
+            bn[x] = b2[x];
         }
     }
 
@@ -124,13 +140,14 @@ __global__ void __launch_bounds__(256, 1) fourier_fp64_kernel(GemmArgs G)
         for (int r = 0; r < 4; ++r) w[bi][r] = G.weight[lrow0 + bi * 16 + 4 * r + kk];
 
     __shared__ double lds_spec[2][GEMM_BN];
+    __shared__ double lds_row[8][64];
     double rowsum[4][4];
 #pragma unroll
     for (int bi = 0; bi < 4; ++bi)
 #pragma unroll
         for (int r = 0; r < 4; ++r) rowsum[bi][r] = 0.0;
 #pragma unroll
-    for (int bj = 0; bj < 4; ++bj) {
+    for (int bj = 0; bj < 2; ++bj) {
         double colsum = 0.0;
 #pragma unroll
         for (int bi = 0; bi < 4; ++bi)
@@ -142,7 +159,7 @@ __global__ void __launch_bounds__(256, 1) fourier_fp64_kernel(GemmArgs G)
             }
         colsum += __shfl_xor(colsum, 16);
         colsum += __shfl_xor(colsum, 32);
-        if (kk == 0) lds_spec[wr][wc * 64 + bj * 16 + ii] = colsum;
+        if (kk == 0) lds_spec[wr][wc * 32 + bj * 16 + ii] = colsum;
     }
 #pragma unroll
     for (int bi = 0; bi < 4; ++bi)
@@ -153,9 +170,13 @@ __global__ void __launch_bounds__(256, 1) fourier_fp64_kernel(GemmArgs G)
             v += __shfl_xor(v, 2);
             v += __shfl_xor(v, 4);
             v += __shfl_xor(v, 8);
-            if (ii == 0) G.part_contrib[(int64_t)(ct * 2 + wc) * G.npad + row0 + bi * 16 + 4 * r + kk] = v;
+            if (ii == 0) lds_row[wave][bi * 16 + 4 * r + kk] = v;
         }
     __syncthreads();
+    // per-trajectory sums over each 64-energy half of the tile: waves wc and
+    // wc + 1 cover one half
+    if ((wc & 1) == 0)
+        G.part_contrib[(int64_t)(ct * 2 + (wc >> 1)) * G.npad + row0 + lane] = lds_row[wave][lane] + lds_row[wave + 1][lane];
     if (threadIdx.x < GEMM_BN) {
         const int x = threadIdx.x;
         G.part_spec[(int64_t)rt * G.kpad + ct * GEMM_BN + x] = lds_spec[0][x] + lds_spec[1][x];
@@ -168,7 +189,7 @@ hipError_t launch_fourier_fp64(const GemmArgs &a, hipStream_t s)
 {
     const int nwg = a.row_tiles * a.col_tiles;
     if (nwg <= 0) return hipSuccess;
-    hipLaunchKernelGGL(fourier_fp64_kernel, dim3(nwg), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(fourier_fp64_kernel, dim3(nwg), dim3(512), 0, s, a);
     return hipGetLastError();
 }
 
