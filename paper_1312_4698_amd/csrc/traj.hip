@@ -71,6 +71,8 @@ struct GroupCore {
     double rS[RB][ST];                 // with OVL: each lane's part of the action; MULTI without OVL: lane 0's
     double rzr[RB], rzi[RB], rinc[RB];
     double rtheta, rphi;               // branch and prefactor phase after the last finished sample
+    double prev_r, prev_i;             // det(A) of the last step, rescaled
+    double detM, maxdev;               // the monitor's last det(M) and largest |det(M)^2 - 1|
     int rflag[RB];
     int rgood;
 };
@@ -143,7 +145,7 @@ traj_kernel(TrajArgs A, const ProblemDev *__restrict__ P0)
     double dpP[F], dqP[F], dpQ[F], dqQ[F];
     R pc, qc;
     Action<MIXED> S;
-    double theta, prev_r, prev_i, phi, detM, maxdev;
+    double theta, prev_r, prev_i, phi, detM, maxdev;  // held in the group's LDS block while the steps run
     int escale = 0;  // amplitude scale exponent (mixed form)
     bool good;
     if (A.step_begin == 0) {
@@ -186,6 +188,14 @@ traj_kernel(TrajArgs A, const ProblemDev *__restrict__ P0)
     }
     qv[c] = qc;
     pm[c] = pc;
+    if (c == 0) {
+        L.rtheta = theta;
+        L.rphi = phi;
+        L.prev_r = prev_r;
+        L.prev_i = prev_i;
+        L.detM = detM;
+        L.maxdev = maxdev;
+    }
     lds_order();
 
     // exponent of <chi|p,q> of the published state
@@ -393,8 +403,10 @@ traj_kernel(TrajArgs A, const ProblemDev *__restrict__ P0)
             }
             const double dM = lu_det_real2<N2, F>(r0, r1, c, L.pivM, L.keys);
             const double dev = fabs(dM * dM - 1.0);
-            detM = dM;
-            if (!(dev <= maxdev)) maxdev = dev;
+            if (c == 0) {
+                L.detM = dM;
+                if (!(dev <= L.maxdev)) L.maxdev = dev;
+            }
             if (!(dev <= Ps->det_tol)) good = false;
         }
         if constexpr (STASH) {
@@ -422,12 +434,13 @@ traj_kernel(TrajArgs A, const ProblemDev *__restrict__ P0)
             (void)frexp(fmax(fabs(dAr), fabs(dAi)), &ex);
             dAr = ldexp(dAr, -ex);
             dAi = ldexp(dAi, -ex);
-            const double ur = dAr * prev_r + dAi * prev_i;
-            const double ui = dAi * prev_r - dAr * prev_i;
+            const double pr_ = L.prev_r, pi_ = L.prev_i;
+            const double ur = dAr * pr_ + dAi * pi_;
+            const double ui = dAi * pr_ - dAr * pi_;
             L.rzr[slot] = ur * Ps->cos_gdt - ui * Ps->sin_gdt;
             L.rzi[slot] = ur * Ps->sin_gdt + ui * Ps->cos_gdt;
-            prev_r = dAr;
-            prev_i = dAi;
+            L.prev_r = dAr;
+            L.prev_i = dAi;
             if constexpr (OVL) {
                 L.rflag[slot] = good ? 1 : 0;  // the finite-action test is on the sum
             } else if constexpr (MULTI) {
@@ -458,7 +471,7 @@ traj_kernel(TrajArgs A, const ProblemDev *__restrict__ P0)
             if (c < cnt) L.rinc[sl] = datan2(L.rzi[sl], L.rzr[sl], &Ps->mc);
             lds_order();
             if (c < cnt) {
-                double th = theta;
+                double th = L.rtheta;
 #pragma unroll
                 for (int u = 0; u < RB; ++u)
                     if (u <= c) th += L.rinc[(first + u) % RB];
@@ -506,8 +519,7 @@ traj_kernel(TrajArgs A, const ProblemDev *__restrict__ P0)
                 }
             }
             lds_order();
-            theta = L.rtheta;
-            phi = L.rphi;
+
             good = L.rgood != 0;
             lds_order();
         }
@@ -534,13 +546,13 @@ traj_kernel(TrajArgs A, const ProblemDev *__restrict__ P0)
         if (c == 0) {
             A.scal[SC_S * NP + jr] = S.hi();
             A.scal[SC_SCOMP * NP + jr] = S.lo();
-            A.scal[SC_THETA * NP + jr] = theta;
-            A.scal[SC_PREV_RE * NP + jr] = prev_r;
-            A.scal[SC_PREV_IM * NP + jr] = prev_i;
-            A.scal[SC_PHI * NP + jr] = phi;
+            A.scal[SC_THETA * NP + jr] = L.rtheta;
+            A.scal[SC_PREV_RE * NP + jr] = L.prev_r;
+            A.scal[SC_PREV_IM * NP + jr] = L.prev_i;
+            A.scal[SC_PHI * NP + jr] = L.rphi;
             A.scal[SC_GOOD * NP + jr] = good ? 1.0 : 0.0;
-            A.scal[SC_DETM * NP + jr] = detM;
-            A.scal[SC_MAXDEV * NP + jr] = maxdev;
+            A.scal[SC_DETM * NP + jr] = L.detM;
+            A.scal[SC_MAXDEV * NP + jr] = L.maxdev;
             A.scal[SC_ESCALE * NP + jr] = (double)escale;
         }
 #pragma unroll
