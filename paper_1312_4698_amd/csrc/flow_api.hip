@@ -44,7 +44,13 @@ struct scivr_flow {
 
 namespace {
 
-constexpr int64_t WGRAD_CHUNK = 512;  // batch rows per split-K partial of the weight gradients
+// Batch rows per split-K partial of the weight gradients: about 64 partials
+// per gradient, so that a batch of a few thousand rows spreads over the whole
+// chip, with 64 to 512 rows in each.
+int64_t wgrad_chunk(int64_t rows)
+{
+    return std::min<int64_t>(512, std::max<int64_t>(64, ((rows + 63) / 64 + 15) / 16 * 16));
+}
 constexpr int FLOW_KIND = 4;          // kernel-time slot of the flow kernels
 
 template <typename T>
@@ -81,7 +87,9 @@ void free_batch(scivr_flow *f)
     f->cap_batch = 0;
 }
 
-int64_t chunks_of(int64_t rows) { return (rows + WGRAD_CHUNK - 1) / WGRAD_CHUNK; }
+int64_t chunks_of(int64_t rows) { return (rows + wgrad_chunk(rows) - 1) / wgrad_chunk(rows); }
+// the most partials any batch of at most B rows takes
+int64_t max_chunks(int64_t B) { return std::max<int64_t>(64, (B + 511) / 512); }
 
 hipError_t ensure_inference(scivr_flow *f, int64_t n)
 {
@@ -125,7 +133,7 @@ hipError_t ensure_batch(scivr_flow *f, int64_t B)
     if (B <= f->cap_batch) return hipSuccess;
     free_batch(f);
     const int F = f->sh.F, H = f->sh.H, L = f->sh.L;
-    const int64_t part = chunks_of(B) * std::max<int64_t>(std::max<int64_t>(2LL * F * (H + 1), (int64_t)H * (H + 1)),
+    const int64_t part = max_chunks(B) * std::max<int64_t>(std::max<int64_t>(2LL * F * (H + 1), (int64_t)H * (H + 1)),
                                                           (int64_t)H * (F + 1));
     hipError_t e;
     if ((e = falloc(&f->t_Z, B * 2 * F)) != hipSuccess) return e;
@@ -211,7 +219,7 @@ hipError_t weight_grad(scivr_flow *f, const float *G, int N, const float *X, int
     g.M = N;
     g.N = K + 1;
     g.K = rows;
-    g.k_chunk = WGRAD_CHUNK;
+    g.k_chunk = wgrad_chunk(rows);
     g.c_stride = (int64_t)N * (K + 1);
     g.ones_col = K;
     g.epi = EPI_PLAIN;

@@ -18,41 +18,35 @@ constexpr double LOG_2PI = 1.8378770664093454836;
 inline unsigned blocks_for(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
 // ---------------------------------------------------------------- FP32 GEMM
-// 64 x 64 output tile per 256-thread workgroup, 4 x 4 outputs per thread,
-// operands staged through LDS in k-slices of 16.
-template <bool AT, bool BNK, int EPI>
-__global__ void __launch_bounds__(256) gemm_f32_kernel(GemmF32 g)
-{
-    __shared__ float As[16][64 + 4];
-    __shared__ float Bs[16][64 + 4];
-    const int tid = threadIdx.x;
-    const int m0 = blockIdx.x * 64, n0 = blockIdx.y * 64;
-    const int64_t kb = (int64_t)blockIdx.z * g.k_chunk;
-    const int64_t ke = min(g.K, kb + g.k_chunk);
-    const int tx = tid & 15, ty = tid >> 4;
-    float acc[4][4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = 0.f;
+// TM x 64 output tile per 256-thread workgroup (TM = 64 or 32), TM / 16 x 4
+// outputs per thread, operands staged through LDS in k-slices of 32.  The
+// next slice's global loads are issued into registers before the current
+// slice is multiplied, so their latency overlaps the arithmetic.  The 32-row
+// tile doubles the workgroups of products too small to fill the chip.  Each
+// output sums its k terms in ascending order.
+constexpr int GEMM_KS = 32;
 
-    for (int64_t k0 = kb; k0 < ke; k0 += 16) {
+template <bool AT, bool BNK, int TM>
+struct F32Slice {
+    static constexpr int NA = TM * GEMM_KS / 256, NB = 64 * GEMM_KS / 256;
+    float a[NA], b[NB];
+
+    __device__ void load(const GemmF32 &g, int tid, int m0, int n0, int64_t k0, int64_t ke)
+    {
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
+        for (int r = 0; r < NA; ++r) {
             const int e = tid + 256 * r;
-            const int mm = AT ? (e & 63) : (e >> 4);
-            const int kk = AT ? (e >> 6) : (e & 15);
+            const int mm = AT ? (e % TM) : (e / GEMM_KS);
+            const int kk = AT ? (e / TM) : (e % GEMM_KS);
             const int m = m0 + mm;
             const int64_t k = k0 + kk;
-            float v = 0.f;
-            if (m < g.M && k < ke) v = AT ? g.A[k * g.lda + m] : g.A[(int64_t)m * g.lda + k];
-            As[kk][mm] = v;
+            a[r] = (m < g.M && k < ke) ? (AT ? g.A[k * g.lda + m] : g.A[(int64_t)m * g.lda + k]) : 0.f;
         }
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
+        for (int r = 0; r < NB; ++r) {
             const int e = tid + 256 * r;
-            const int nn = BNK ? (e >> 4) : (e & 63);
-            const int kk = BNK ? (e & 15) : (e >> 6);
+            const int nn = BNK ? (e / GEMM_KS) : (e & 63);
+            const int kk = BNK ? (e % GEMM_KS) : (e >> 6);
             const int n = n0 + nn;
             const int64_t k = k0 + kk;
             float v = 0.f;
@@ -62,18 +56,57 @@ __global__ void __launch_bounds__(256) gemm_f32_kernel(GemmF32 g)
                 else
                     v = BNK ? g.B[(int64_t)n * g.ldb + k] : g.B[k * g.ldb + n];
             }
-            Bs[kk][nn] = v;
+            b[r] = v;
         }
+    }
+
+    __device__ void store(float (*As)[TM + 4], float (*Bs)[64 + 4], int tid) const
+    {
+#pragma unroll
+        for (int r = 0; r < NA; ++r) {
+            const int e = tid + 256 * r;
+            As[AT ? (e / TM) : (e % GEMM_KS)][AT ? (e % TM) : (e / GEMM_KS)] = a[r];
+        }
+#pragma unroll
+        for (int r = 0; r < NB; ++r) {
+            const int e = tid + 256 * r;
+            Bs[BNK ? (e % GEMM_KS) : (e >> 6)][BNK ? (e / GEMM_KS) : (e & 63)] = b[r];
+        }
+    }
+};
+
+template <bool AT, bool BNK, int EPI, int TM>
+__global__ void __launch_bounds__(256) gemm_f32_kernel(GemmF32 g)
+{
+    constexpr int RI = TM / 16;  // rows per thread
+    __shared__ float As[GEMM_KS][TM + 4];
+    __shared__ float Bs[GEMM_KS][64 + 4];
+    const int tid = threadIdx.x;
+    const int m0 = blockIdx.x * TM, n0 = blockIdx.y * 64;
+    const int64_t kb = (int64_t)blockIdx.z * g.k_chunk;
+    const int64_t ke = min(g.K, kb + g.k_chunk);
+    const int tx = tid & 15, ty = tid >> 4;
+    float acc[RI][4];
+#pragma unroll
+    for (int i = 0; i < RI; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = 0.f;
+
+    F32Slice<AT, BNK, TM> sl;
+    sl.load(g, tid, m0, n0, kb, ke);
+    for (int64_t k0 = kb; k0 < ke; k0 += GEMM_KS) {
+        sl.store(As, Bs, tid);
         __syncthreads();
+        if (k0 + GEMM_KS < ke) sl.load(g, tid, m0, n0, k0 + GEMM_KS, ke);
 #pragma unroll
-        for (int kk = 0; kk < 16; ++kk) {
-            float a[4], b[4];
+        for (int kk = 0; kk < GEMM_KS; ++kk) {
+            float a[RI], b[4];
 #pragma unroll
-            for (int i = 0; i < 4; ++i) a[i] = As[kk][ty * 4 + i];
+            for (int i = 0; i < RI; ++i) a[i] = As[kk][ty * RI + i];
 #pragma unroll
             for (int j = 0; j < 4; ++j) b[j] = Bs[kk][tx * 4 + j];
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
+            for (int i = 0; i < RI; ++i)
 #pragma unroll
                 for (int j = 0; j < 4; ++j) acc[i][j] = fmaf(a[i], b[j], acc[i][j]);
         }
@@ -81,8 +114,8 @@ __global__ void __launch_bounds__(256) gemm_f32_kernel(GemmF32 g)
     }
     float *C = g.C + (int64_t)blockIdx.z * g.c_stride;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const int m = m0 + ty * 4 + i;
+    for (int i = 0; i < RI; ++i) {
+        const int m = m0 + ty * RI + i;
         if (m >= g.M) continue;
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
@@ -100,16 +133,27 @@ __global__ void __launch_bounds__(256) gemm_f32_kernel(GemmF32 g)
     }
 }
 
-template <bool AT, bool BNK>
+template <bool AT, bool BNK, int TM>
 hipError_t gemm_epi(const GemmF32 &g, dim3 grid, hipStream_t s)
 {
     switch (g.epi) {
-    case EPI_BIAS_TANH: hipLaunchKernelGGL((gemm_f32_kernel<AT, BNK, EPI_BIAS_TANH>), grid, dim3(256), 0, s, g); break;
-    case EPI_BIAS: hipLaunchKernelGGL((gemm_f32_kernel<AT, BNK, EPI_BIAS>), grid, dim3(256), 0, s, g); break;
-    case EPI_DTANH: hipLaunchKernelGGL((gemm_f32_kernel<AT, BNK, EPI_DTANH>), grid, dim3(256), 0, s, g); break;
-    default: hipLaunchKernelGGL((gemm_f32_kernel<AT, BNK, EPI_PLAIN>), grid, dim3(256), 0, s, g); break;
+    case EPI_BIAS_TANH:
+        hipLaunchKernelGGL((gemm_f32_kernel<AT, BNK, EPI_BIAS_TANH, TM>), grid, dim3(256), 0, s, g);
+        break;
+    case EPI_BIAS: hipLaunchKernelGGL((gemm_f32_kernel<AT, BNK, EPI_BIAS, TM>), grid, dim3(256), 0, s, g); break;
+    case EPI_DTANH: hipLaunchKernelGGL((gemm_f32_kernel<AT, BNK, EPI_DTANH, TM>), grid, dim3(256), 0, s, g); break;
+    default: hipLaunchKernelGGL((gemm_f32_kernel<AT, BNK, EPI_PLAIN, TM>), grid, dim3(256), 0, s, g); break;
     }
     return hipGetLastError();
+}
+
+template <int TM>
+hipError_t gemm_tiles(const GemmF32 &g, hipStream_t s)
+{
+    const int64_t chunks = (g.K + g.k_chunk - 1) / g.k_chunk;
+    const dim3 grid(blocks_for(g.M, TM), blocks_for(g.N, 64), (unsigned)chunks);
+    if (g.a_trans) return g.b_nk ? gemm_epi<true, true, TM>(g, grid, s) : gemm_epi<true, false, TM>(g, grid, s);
+    return g.b_nk ? gemm_epi<false, true, TM>(g, grid, s) : gemm_epi<false, false, TM>(g, grid, s);
 }
 
 // ---------------------------------------------------------------- BF16 GEMM
@@ -327,13 +371,30 @@ __global__ void add_cond_kernel(float *G, const float *GA, int64_t n, int F, int
 }
 
 // Sum the split-K partials [chunks][N][K + 1] in chunk order: column K is the bias gradient.
-__global__ void reduce_wgrad_kernel(const float *part, int chunks, int N, int K, float *gW, float *gb)
+// Sum of the split-K partials.  A workgroup takes 64 consecutive entries;
+// its four waves sum the partials z = w, w + 4, ... in order, and wave 0 adds
+// the four sums in wave order, so the result does not depend on timing.
+__global__ void __launch_bounds__(256) reduce_wgrad_kernel(const float *part, int chunks, int N, int K, float *gW,
+                                                           float *gb)
 {
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    __shared__ float sums[4][64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t idx = (int64_t)blockIdx.x * 64 + lane;
     const int64_t per = (int64_t)N * (K + 1);
-    if (idx >= per) return;
     float s = 0.f;
-    for (int z = 0; z < chunks; ++z) s += part[(int64_t)z * per + idx];
+    if (idx < per) {
+        int z = w;
+        for (; z + 12 < chunks; z += 16) {
+            const float a = part[(int64_t)z * per + idx], b = part[(int64_t)(z + 4) * per + idx];
+            const float c = part[(int64_t)(z + 8) * per + idx], d = part[(int64_t)(z + 12) * per + idx];
+            s = (((s + a) + b) + c) + d;
+        }
+        for (; z < chunks; z += 4) s += part[(int64_t)z * per + idx];
+    }
+    sums[w][lane] = s;
+    __syncthreads();
+    if (w != 0 || idx >= per) return;
+    s = ((sums[0][lane] + sums[1][lane]) + sums[2][lane]) + sums[3][lane];
     const int nn = (int)(idx / (K + 1)), k = (int)(idx % (K + 1));
     if (k < K)
         gW[(int64_t)nn * K + k] = s;
@@ -514,10 +575,8 @@ hipError_t launch_flow_init_params(float *p, int F, int H, int L, uint64_t seed,
 hipError_t launch_gemm_f32(const GemmF32 &g, hipStream_t s)
 {
     if (g.M <= 0 || g.N <= 0 || g.K <= 0) return hipSuccess;
-    const int64_t chunks = (g.K + g.k_chunk - 1) / g.k_chunk;
-    const dim3 grid(blocks_for(g.M, 64), blocks_for(g.N, 64), (unsigned)chunks);
-    if (g.a_trans) return g.b_nk ? gemm_epi<true, true>(g, grid, s) : gemm_epi<true, false>(g, grid, s);
-    return g.b_nk ? gemm_epi<false, true>(g, grid, s) : gemm_epi<false, false>(g, grid, s);
+    const int64_t tiles = (int64_t)blocks_for(g.M, 64) * blocks_for(g.N, 64) * ((g.K + g.k_chunk - 1) / g.k_chunk);
+    return tiles < 512 ? gemm_tiles<32>(g, s) : gemm_tiles<64>(g, s);
 }
 
 hipError_t launch_gemm_bf16(const float *X, int64_t ldx, const uint16_t *W, const float *bias, float *Y, int64_t ldy,
@@ -598,7 +657,7 @@ hipError_t launch_flow_add_cond(float *G, const float *GA, int64_t n, int F, int
 hipError_t launch_flow_reduce_wgrad(const float *part, int chunks, int N, int K, float *gW, float *gb, hipStream_t s)
 {
     const int64_t per = (int64_t)N * (K + 1);
-    hipLaunchKernelGGL(reduce_wgrad_kernel, dim3(blocks_for(per, 256)), dim3(256), 0, s, part, chunks, N, K, gW, gb);
+    hipLaunchKernelGGL(reduce_wgrad_kernel, dim3(blocks_for(per, 64)), dim3(256), 0, s, part, chunks, N, K, gW, gb);
     return hipGetLastError();
 }
 
