@@ -362,13 +362,16 @@ def learned_study(scivr, inputs, peaks, prob, ref_I, sizes, seeds, n_train, laye
     flow = scivr.Flow(ctx, layers, width, seed=5)
     ctx.reset_spectrum()
     ctx.run(seed=4242, n_traj=n_train, first_index=2 * base)
+    ctx.read_totals()  # waits for the training batch: its time is counted apart, at the measured throughput
     t0 = time.perf_counter()
     loss = flow.train_on_batch(epochs=epochs, batch=batch, lr=lr)
     t_train = time.perf_counter() - t0
     info = {}
 
     def draw_flow(sd, N):
-        ess, used = flow.sample(seed=sd, n_traj=N, first_index=base, alpha=alpha)
+        t = time.perf_counter()
+        ess, used = flow.sample(seed=sd, n_traj=N, first_index=base, alpha=alpha)  # returns after the draw
+        info.setdefault("sample_s_per_point", []).append((time.perf_counter() - t) / N)
         info.setdefault("ess", []).append(ess)
         info.setdefault("used", []).append(used)
 
@@ -392,7 +395,9 @@ def learned_study(scivr, inputs, peaks, prob, ref_I, sizes, seeds, n_train, laye
         "flow": {"layers": layers, "width": width, "params": int(FLOW_PARAMS(prob.F, width, layers)),
                  "n_train": n_train, "epochs": epochs, "batch": batch, "lr": lr, "alpha": alpha,
                  "final_loss": loss, "train_s": t_train, "ess_min": float(min(info["ess"])),
-                 "ess_median": float(np.median(info["ess"])), "fallbacks": int(sum(1 for u in info["used"] if not u))},
+                 "ess_median": float(np.median(info["ess"])), "fallbacks": int(sum(1 for u in info["used"] if not u)),
+                 # drawing from the mixture, at the sweep's largest N
+                 "sample_s_per_point": float(np.median(info["sample_s_per_point"][len(sizes) - 1::len(sizes)]))},
         "sweep_s": {"plain": t_plain, "learned": t_learned},
     }
 
@@ -840,6 +845,7 @@ def main():
         vp, vm = out["plain_fp64"]["value"], value
         n_plain, n_learn = lp["plain"]["N_to_1cm"], lp["learned"]["N_to_1cm"]
         train_s = lp["flow"]["train_s"] + lp["flow"]["n_train"] * prob.n_steps / vm
+        draw_s = lp["flow"]["sample_s_per_point"]
         both = n_plain is not None and n_learn is not None
         out["time_to_1cm"] = {
             "equal_variance_speedup": lp["variance_ratio_plain_over_learned"] * vm / vp,
@@ -849,14 +855,14 @@ def main():
                 / out["energy"]["J_per_step"]),
             # only when both sides reach 1 cm^-1 within the sweep
             "plain_fp64_s": n_plain * prob.n_steps / vp if both else None,
-            "mixed_learned_s": n_learn * prob.n_steps / vm + train_s if both else None,
+            "mixed_learned_s": n_learn * (prob.n_steps / vm + draw_s) + train_s if both else None,
             "fit_plain_fp64_s": (None if lp["plain"]["N_to_1cm_fit"] is None else
                                  lp["plain"]["N_to_1cm_fit"] * prob.n_steps / vp),
             "fit_mixed_learned_s": (None if lp["learned"]["N_to_1cm_fit"] is None else
-                                    lp["learned"]["N_to_1cm_fit"] * prob.n_steps / vm + train_s),
+                                    lp["learned"]["N_to_1cm_fit"] * (prob.n_steps / vm + draw_s) + train_s),
             "mixed_learned_training_s": train_s,
             "note": ("plain: FP64 path with Husimi sampling; mixed_learned: mixed path with the learned proposal, "
-                     "including its training batch and training time; equal_variance_speedup = (plain/learned "
+                     "including its training batch, training time and the draws from the mixture; equal_variance_speedup = (plain/learned "
                      "spectrum variance at equal N) x (mixed/plain throughput); fit_*: from the N^-1/2 fit of the "
                      "median peak error"),
         }

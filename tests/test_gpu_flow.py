@@ -96,7 +96,10 @@ def test_flow_density_matches_oracle(scivr, oracle_mod, F, H):
     ctx.close()
 
 
-@pytest.mark.parametrize("F,H,n", [(3, 16, 700), (9, 128, 2000), (30, 256, 1500)])
+@pytest.mark.parametrize("F,H,n", [
+    (3, 16, 700), (9, 128, 2000), (30, 256, 1500),
+    (3, 16, 40000),  # 512-row weight-gradient partials with a ragged last one; 64-row GEMM tiles
+])
 def test_flow_gradient_matches_oracle(scivr, oracle_mod, F, H, n):
     L = 4
     prob = inputs.morse_quartic(F, F, n_steps=8, n_energies=8)
