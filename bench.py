@@ -54,6 +54,13 @@ def traj_flops_per_step(F: int) -> float:
     return float(drift + kick + detm + pref + deta + amp)
 
 
+def full_flops_per_segment_step(F: int) -> float:
+    """Algorithmic FP64 flops of one segment step of the double-time form of
+    Eq. (9): the trajectory step without the monitor's real elimination
+    (segments are not monitored), plus the product with conj(<chi|z(c1)>)."""
+    return traj_flops_per_step(F) - (2.0 / 3.0) * (2 * F) ** 3 + 6.0
+
+
 def fourier_flops(n_traj: int, n_times: int, K: int) -> float:
     """8 flops per complex multiply-add of amp[j][c] exp(i E_k c dt)."""
     return 8.0 * n_traj * n_times * K
@@ -249,6 +256,126 @@ def fft_form(scivr, torch, prob, n, seed=4321):
     (g_ms, Ig), (f_ms, If) = res["gemm"], res["fft"]
     return {"gemm_ms": g_ms, "fft_ms": f_ms, "speedup": g_ms / f_ms,
             "max_rel_diff": float(np.max(np.abs(If - Ig)) / np.max(np.abs(Ig)))}
+
+
+def refs_form(scivr, torch, inputs, n=65536, n_refs=8, reps=2, cpu_sample=64, seed=777):
+    """Several reference states on one batch (scivr_set_references), F = 9
+    FP64, 4096 steps, 2048 energies: whole passes with all n_refs states
+    against passes with chi alone, the multi-reference trajectory kernel's
+    rate against the FP64 vector peak, the Fourier GEMM (one right-hand side
+    per state) against the FP64 matrix peak, and the oracle (one run per
+    state, as it stands) on a bounded sample on the host cores."""
+    from oracle import oracle as O
+    prob, _ = inputs.workload("F9_fp64")
+    rng = np.random.default_rng(seed)
+    sg = np.sqrt(prob.gamma)
+    pe = rng.uniform(-0.8, 0.8, (n_refs - 1, prob.F)) * sg
+    qe = rng.uniform(-0.8, 0.8, (n_refs - 1, prob.F)) / sg
+    stream = torch.cuda.current_stream()
+    res = {}
+    for key, k in (("chi_only", 1), ("all_states", n_refs)):
+        ctx = scivr.Context(prob, max_traj=n)
+        if k > 1:
+            ctx.set_references(pe, qe)
+
+        def one(i):
+            ctx.sample_husimi(seed=seed + i, n_traj=n, stream=stream)
+            ctx.propagate(0, prob.n_steps, stream=stream)
+            ctx.accumulate(stream=stream)
+
+        one(0)
+        torch.cuda.synchronize()
+        ctx.reset_spectrum(stream=stream)
+        ctx.timing(True)
+        t0 = time.perf_counter()
+        for i in range(reps):
+            one(1 + i)
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t0) / reps
+        kt = ctx.kernel_times()
+        ctx.close()
+        res[key] = {"wall_s": wall, "traj_ms": kt["trajectory"][1] / max(kt["trajectory"][0], 1),
+                    "fourier_ms": kt["fourier"][1] / max(kt["fourier"][0], 1)}
+        print(f"[bench] several reference states: {k} state(s), {wall:.3f} s per pass", file=sys.stderr, flush=True)
+    a = res["all_states"]
+    steps = n * prob.n_steps
+    fl_traj = steps * (traj_flops_per_step(prob.F) + (n_refs - 1) * (12 * prob.F + 10))
+    fl_four = n_refs * fourier_flops(n, prob.n_steps + 1, prob.n_energies)
+    achieved = fl_traj / (a["traj_ms"] / 1e3) / 1e12
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    p0, q0, lr = O.sample_husimi(prob, seed, cpu_sample)
+    t0 = time.perf_counter()
+    for m in range(n_refs):
+        pm = prob if m == 0 else prob.replace(p_eq=pe[m - 1], q_eq=qe[m - 1])
+        O.run(pm, p0, q0, lr, want_state=False, want_contrib=False, n_threads=threads)
+    cpu = time.perf_counter() - t0
+    return {
+        "workload": f"F9_fp64 with {n_refs} reference states (chi and {n_refs - 1} displaced), {n} Husimi "
+                    f"trajectories, {prob.n_steps} steps, {prob.n_energies} energies",
+        "value": steps / a["wall_s"], "unit": "trajectory-steps/s (every state's spectrum)",
+        "chi_only_value": steps / res["chi_only"]["wall_s"],
+        "passes": res,
+        "roofline": {"kernel": "traj_kernel (multi-reference variant)", "bound": "alu", "achieved": achieved,
+                     "peak": FP64_VALU_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": achieved / FP64_VALU_PEAK_TFLOPS,
+                     "flops_per_launch": fl_traj},
+        "fourier": {"kernel": "fourier_fp64_kernel", "bound": "mfma",
+                    "achieved_TFLOPs": fl_four / (a["fourier_ms"] / 1e3) / 1e12,
+                    "peak_TFLOPs": FP64_MFMA_PEAK_TFLOPS},
+        "cpu_baseline": {"value": cpu_sample * prob.n_steps / cpu, "unit": "trajectory-steps/s (every state)",
+                         "cores": threads, "kind": "oracle",
+                         "sample": f"{cpu_sample} trajectories, one oracle run per state ({n_refs}), {cpu:.1f} s wall"},
+    }
+
+
+def full_form_study(scivr, torch, inputs, n=4096, n_steps=512, reps=2, cpu_sample=32, seed=888):
+    """The double-time form of Eq. (9) (scivr_accumulate_spectrum_full), F = 9
+    FP64, n_steps steps: segment-steps/s of the double-time kernel against the
+    FP64 vector peak, whole passes (sample + propagate + double-time
+    accumulation), and the oracle's double-time form on a bounded sample."""
+    from oracle import oracle as O
+    prob = inputs.workload("F9_fp64")[0].replace(n_steps=n_steps)
+    stream = torch.cuda.current_stream()
+    ctx = scivr.Context(prob, max_traj=n)
+
+    def one(i):
+        ctx.sample_husimi(seed=seed + i, n_traj=n, stream=stream)
+        ctx.propagate(0, prob.n_steps, stream=stream)
+        ctx.accumulate_full(stream=stream)
+
+    one(0)
+    torch.cuda.synchronize()
+    ctx.reset_spectrum(stream=stream)
+    ctx.timing(True)
+    t0 = time.perf_counter()
+    for i in range(reps):
+        one(1 + i)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / reps
+    kt = ctx.kernel_times()
+    ctx.close()
+    full_ms = kt["fourier"][1] / max(kt["fourier"][0], 1)
+    seg = n * n_steps * (n_steps + 1) / 2  # segment steps: sum over c1 of (n_steps - c1)
+    fl = seg * full_flops_per_segment_step(prob.F)
+    achieved = fl / (full_ms / 1e3) / 1e12
+    print(f"[bench] double-time form: {wall:.3f} s per pass, {full_ms:.1f} ms in the double-time kernels",
+          file=sys.stderr, flush=True)
+    p0, q0, lr = O.sample_husimi(prob, seed, cpu_sample)
+    t0 = time.perf_counter()
+    O.run_full(prob, p0, q0, lr)
+    cpu = time.perf_counter() - t0
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {
+        "workload": f"F9_fp64 at {n_steps} steps, double-time form of Eq. (9): {n} Husimi trajectories, "
+                    f"{prob.n_energies} energies",
+        "value": seg / (full_ms / 1e3), "unit": "segment-steps/s",
+        "pass_s": wall, "double_time_ms": full_ms, "segment_steps_per_pass": seg,
+        "roofline": {"kernel": "ta_full_kernel (with the lag sums and the spectrum)", "bound": "alu",
+                     "achieved": achieved, "peak": FP64_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / FP64_VALU_PEAK_TFLOPS, "flops_per_launch": fl},
+        "cpu_baseline": {"value": cpu_sample * n_steps * (n_steps + 1) / 2 / cpu, "unit": "segment-steps/s",
+                         "cores": threads, "kind": "oracle",
+                         "sample": f"{cpu_sample} trajectories of the same problem, {cpu:.1f} s wall"},
+    }
 
 
 def _peak_error_cm(peaks, inputs, E, T, ref_peaks, I):
@@ -690,6 +817,10 @@ def main():
                     help="only time the oracle over this whole workload on the host cores and exit")
     ap.add_argument("--sweep", default="",
                     help="only run the throughput sweep of this workload over N = 2^7 .. 2^18 and exit")
+    ap.add_argument("--next-rows", type=int, default=1,
+                    help="also measure several reference states on one batch and the double-time form (1) or not (0)")
+    ap.add_argument("--next-rows-only", type=int, default=0,
+                    help="only measure several reference states and the double-time form, and exit")
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="only copy this many bytes device-to-device (counter calibration) and exit")
     args = ap.parse_args()
@@ -725,6 +856,10 @@ def main():
     if args.sweep:
         res = x1_sweep(scivr, torch, inputs, args.sweep, range(7, 19))
         print(json.dumps({"sweep_summary": res}))
+        return
+    if args.next_rows_only:
+        print(json.dumps({"several_references": refs_form(scivr, torch, inputs),
+                          "double_time_form": full_form_study(scivr, torch, inputs)}))
         return
     prob, n = inputs.workload(args.workload)
     if args.n_traj:
@@ -882,6 +1017,13 @@ def main():
         out["fft_fourier"]["note"] = ("exact FFT autocorrelation form of the Fourier step (scivr_accumulate_spectrum_fft) "
                                       "on one batch of identical trajectories; value_with_fft = trajectory-steps/s "
                                       "with the measured trajectory kernel time and the FFT form in place of the GEMM")
+    if args.next_rows and prob.F <= 16:
+        # separate lines for the rows beyond the single-state, separable path
+        for key, fn in (("several_references", refs_form), ("double_time_form", full_form_study)):
+            try:
+                out[key] = fn(scivr, torch, inputs)
+            except Exception as e:  # reported in the line instead of losing the headline
+                out[key] = {"error": f"{type(e).__name__}: {e}"}
     if args.cpu_sample > 0:
         print(f"[bench] cpu baseline: oracle on {args.cpu_sample} trajectories", file=sys.stderr, flush=True)
         pprob = prob.replace(precision=inputs.PRECISION_FP64)

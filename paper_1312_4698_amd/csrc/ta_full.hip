@@ -149,8 +149,17 @@ __device__ inline double overlap_of(ConstProblem P, const FullGroupLds<F> &L, do
     return ex;
 }
 
+// Waves per SIMD the register allocator must allow (unified 512-register
+// file).  For 7 <= F <= 12 the kernel needs more than 256 registers and would
+// run one wave per SIMD, where nothing hides the LDS round trips of the
+// eliminations; two waves with some spilling are faster.  Smaller F already
+// fits two or more waves.
 template <int F>
-__global__ void __launch_bounds__(64) ta_full_kernel(FullArgs A, const ProblemDev *__restrict__ P0)
+constexpr int full_waves() { return (F >= 7 && F <= 12) ? 2 : 1; }
+
+template <int F>
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(full_waves<F>(), 8)))
+ta_full_kernel(FullArgs A, const ProblemDev *__restrict__ P0)
 {
     constexpr int W = 64 / F;
     __shared__ FullGroupLds<F> lds_all[W];
