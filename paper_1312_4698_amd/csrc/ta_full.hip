@@ -46,9 +46,14 @@ namespace {
 
 template <int F>
 struct alignas(16) FullGroupLds {
+    static constexpr int RB = F < 8 ? F : 8;  // lags per ring
     double pivA[2 * F];
     unsigned keys[(F + 3) & ~3];
     double qv[F], pm[F], ph[F], pv[F];
+    // ring of the last RB lags: each mode's q and p, the raw det(A), the
+    // action, and the argument that advances the branch
+    double rq[RB][F], rp[RB][F];
+    double rdr[RB], rdi[RB], rS[RB], ra[RB];
 };
 
 // One fourth-order triple-jump step of the group's trajectory: positions,
@@ -133,20 +138,29 @@ __device__ inline void full_step(const ProblemDev *P0, FullGroupLds<F> &L, const
     }
 }
 
-// exponent and phase of <chi|p,q> of the group's published state
+// exponent and phase of <chi|p,q> for the modes' positions q[i] and momenta p[i]
 template <int F>
-__device__ inline double overlap_of(ConstProblem P, const FullGroupLds<F> &L, double &ph)
+__device__ inline double overlap_of(ConstProblem P, const double *q, const double *p, double &ph)
 {
     double ex = 0.0;
     ph = 0.0;
 #pragma unroll
     for (int i = 0; i < F; ++i) {
-        const double dqe = P->q_eq[i] - L.qv[i];
-        const double dpe = P->p_eq[i] - L.pm[i];
+        const double dqe = P->q_eq[i] - q[i];
+        const double dpe = P->p_eq[i] - p[i];
         ex += -0.25 * P->gamma[i] * dqe * dqe - dpe * dpe * P->inv4gamma[i];
-        ph += 0.5 * dqe * (P->p_eq[i] + L.pm[i]);
+        ph += 0.5 * dqe * (P->p_eq[i] + p[i]);
     }
     return ex;
+}
+
+// det(A) rescaled by a power of two (the branch only needs its argument)
+__device__ inline void rescale(double &dr, double &di)
+{
+    int e2;
+    (void)frexp(fmax(fabs(dr), fabs(di)), &e2);
+    dr = ldexp(dr, -e2);
+    di = ldexp(di, -e2);
 }
 
 // Waves per SIMD the register allocator must allow (unified 512-register
@@ -164,7 +178,8 @@ ta_full_kernel(FullArgs A, const ProblemDev *__restrict__ P0)
     constexpr int W = 64 / F;
     __shared__ FullGroupLds<F> lds_all[W];
     __shared__ double lam_lds[F * F];
-    __shared__ double2 term[W];
+    constexpr int RB = FullGroupLds<F>::RB;
+    __shared__ double2 term[W][RB];
     const int lane = threadIdx.x;
     for (int idx = lane; idx < F * F; idx += 64) lam_lds[idx] = P0->lam[(idx / F) * FMAX + idx % F];
     const int g = lane / F;
@@ -209,69 +224,116 @@ ta_full_kernel(FullArgs A, const ProblemDev *__restrict__ P0)
         L.qv[c] = qc;
         lds_order();
         double ph1;
-        const double ex1 = overlap_of<F>(P, L, ph1);  // <chi|z(c1)>
+        const double ex1 = overlap_of<F>(P, L.qv, L.pm, ph1);  // <chi|z(c1)>
+        // the branch through the lags finished so far: theta, and det(A) of the
+        // last of them rescaled (kept by the lanes c < RB that finish lags)
         double theta = 0.0, prev_r = 1.0, prev_i = 0.0;
         const int len = ns - r * W;  // lags of the round's longest segment (g = 0)
-        for (int tau = 0; tau <= len; ++tau) {
+        {
+            // lag 0: C = 1, (1/2) |<chi|z(c1)>|^2
             ConstProblem Ps = opaque(P0);
-            double xr = 0.0, xi = 0.0;
-            if (tau == 0) {
-                if (c == 0) xr = 0.5 * dexp(2.0 * ex1, &Ps->mc);  // C = 1: (1/2) |<chi|z(c1)>|^2
-            } else {
-                full_step<F, true>(P0, L, lam_lds, c, pc, qc, S, dpP, dqP, dpQ, dqQ);
-                double are[F], aim[F];
-#pragma unroll
-                for (int i = 0; i < F; ++i) {
-                    const double si = Ps->sqrt_gamma[i], isi = Ps->inv_sqrt_gamma[i];
-                    are[i] = 0.5 * (si * dqQ[i] * isgc + dpP[i] * sgc * isi);
-                    aim[i] = 0.5 * (-si * dqP[i] * sgc + dpQ[i] * isi * isgc);
-                }
-                double dAr, dAi;
-                lu_det_complex<F>(are, aim, c, L.pivA, L.keys, dAr, dAi);
-                if (c == 0) {
-                    // |C| = |det A|^(1/2); the branch as in the propagation: theta
-                    // accumulates the principal argument of det(A_t) conj(det(A_{t-dt}))
-                    // e^{i dt sum gamma}, on det(A) rescaled by a power of two
-                    const double mod = sqrt(hypot(dAr, dAi));
-                    int e2;
-                    (void)frexp(fmax(fabs(dAr), fabs(dAi)), &e2);
-                    dAr = ldexp(dAr, -e2);
-                    dAi = ldexp(dAi, -e2);
-                    const double ur = dAr * prev_r + dAi * prev_i;
-                    const double ui = dAi * prev_r - dAr * prev_i;
-                    const double zr = ur * Ps->cos_gdt - ui * Ps->sin_gdt;
-                    const double zi = ur * Ps->sin_gdt + ui * Ps->cos_gdt;
-                    prev_r = dAr;
-                    prev_i = dAi;
-                    theta += datan2(zi, zr, &Ps->mc);
-                    const double phi = 0.5 * (theta - Ps->sum_gamma * ((double)tau * Ps->dt));
-                    double ph;
-                    const double ex = overlap_of<F>(Ps, L, ph);
-                    const double mag = mod * dexp(ex + ex1, &Ps->mc);
-                    double sn, cs;
-                    dsincos(phi + ph + S - ph1, &Ps->mc, &sn, &cs);
-                    xr = mag * cs;
-                    xi = mag * sn;
-                }
-            }
-            // the groups' terms of this lag, summed in group order by lane 0
-            const bool live = seg && c1 + tau <= ns && isfinite(xr) && isfinite(xi);
+            const double x0 = (c == 0) ? 0.5 * dexp(2.0 * ex1, &Ps->mc) : 0.0;
+            const bool live = seg && isfinite(x0);
             lds_order();
-            if (c == 0) term[g] = make_double2(live ? xr : 0.0, live ? xi : 0.0);
+            if (c == 0) term[g][0] = make_double2(live ? x0 : 0.0, 0.0);
             lds_order();
             if (lane == 0) {
                 double sr = 0.0, si = 0.0;
                 for (int gg = 0; gg < W; ++gg) {
-                    sr += term[gg].x;
-                    si += term[gg].y;
+                    sr += term[gg][0].x;
+                    si += term[gg][0].y;
                 }
-                double2 *o = out + (int64_t)tau * NP;
+                double2 *o = out;
                 double2 v = *o;
                 v.x += sr;
                 v.y += si;
                 *o = v;
             }
             lds_order();
+        }
+        int nk = 0;  // lags in the ring
+        for (int tau = 1; tau <= len; ++tau) {
+            ConstProblem Ps = opaque(P0);
+            full_step<F, true>(P0, L, lam_lds, c, pc, qc, S, dpP, dqP, dpQ, dqQ);
+            double are[F], aim[F];
+#pragma unroll
+            for (int i = 0; i < F; ++i) {
+                const double si = Ps->sqrt_gamma[i], isi = Ps->inv_sqrt_gamma[i];
+                are[i] = 0.5 * (si * dqQ[i] * isgc + dpP[i] * sgc * isi);
+                aim[i] = 0.5 * (-si * dqP[i] * sgc + dpQ[i] * isi * isgc);
+            }
+            double dAr, dAi;
+            lu_det_complex<F>(are, aim, c, L.pivA, L.keys, dAr, dAi);
+            L.rq[nk][c] = qc;
+            L.rp[nk][c] = pc;
+            if (c == 0) {
+                L.rdr[nk] = dAr;
+                L.rdi[nk] = dAi;
+                L.rS[nk] = S;
+            }
+            ++nk;
+            if (nk < RB && tau < len) continue;
+            // Finish the ring's lags tau0 .. tau0 + nk - 1, lane c < nk taking
+            // lag tau0 + c: |C| = |det A|^(1/2); the branch as in the
+            // propagation (theta accumulates the principal argument of
+            // det(A_t) conj(det(A_{t-dt})) e^{i dt sum gamma}, on det(A) rescaled
+            // by a power of two), its arguments added in lag order.
+            const int tau0 = tau - nk + 1;
+            lds_order();
+            double mod = 0.0;
+            if (c < nk) {
+                double dr = L.rdr[c], di = L.rdi[c];
+                mod = sqrt(hypot(dr, di));
+                rescale(dr, di);
+                double qr = prev_r, qi = prev_i;
+                if (c > 0) {
+                    qr = L.rdr[c - 1];
+                    qi = L.rdi[c - 1];
+                    rescale(qr, qi);
+                }
+                const double ur = dr * qr + di * qi;
+                const double ui = di * qr - dr * qi;
+                const double zr = ur * Ps->cos_gdt - ui * Ps->sin_gdt;
+                const double zi = ur * Ps->sin_gdt + ui * Ps->cos_gdt;
+                L.ra[c] = datan2(zi, zr, &Ps->mc);
+            }
+            lds_order();
+            if (c < nk) {
+                const int tk = tau0 + c;
+                double th = theta;
+                for (int kk = 0; kk <= c; ++kk) th += L.ra[kk];
+                const double phi = 0.5 * (th - Ps->sum_gamma * ((double)tk * Ps->dt));
+                double ph;
+                const double ex = overlap_of<F>(Ps, L.rq[c], L.rp[c], ph);
+                const double mag = mod * dexp(ex + ex1, &Ps->mc);
+                double sn, cs;
+                dsincos(phi + ph + L.rS[c] - ph1, &Ps->mc, &sn, &cs);
+                const double xr = mag * cs, xi = mag * sn;
+                const bool live = seg && c1 + tk <= ns && isfinite(xr) && isfinite(xi);
+                term[g][c] = make_double2(live ? xr : 0.0, live ? xi : 0.0);
+                // the branch carried to the next ring (the same on every such lane)
+                for (int kk = c + 1; kk < nk; ++kk) th += L.ra[kk];
+                theta = th;
+                prev_r = L.rdr[nk - 1];
+                prev_i = L.rdi[nk - 1];
+                rescale(prev_r, prev_i);
+            }
+            lds_order();
+            // the groups' terms of each lag, summed in group order by lane tau - tau0
+            if (lane < nk) {
+                double sr = 0.0, si = 0.0;
+                for (int gg = 0; gg < W; ++gg) {
+                    sr += term[gg][lane].x;
+                    si += term[gg][lane].y;
+                }
+                double2 *o = out + (int64_t)(tau0 + lane) * NP;
+                double2 v = *o;
+                v.x += sr;
+                v.y += si;
+                *o = v;
+            }
+            lds_order();
+            nk = 0;
         }
     }
 }
