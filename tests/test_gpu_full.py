@@ -50,6 +50,8 @@ def _gpu_full(S, prob, p0, q0, lr):
     (3, 12, 64, 100, 0.06),
     (6, 6, 40, 80, 0.1),
     (9, 4, 30, 64, 0.1),
+    (12, 3, 21, 48, 0.15),     # two waves per SIMD with a spill; rounds of 5 segments
+    (16, 2, 19, 48, 0.2),      # one wave per SIMD; 4 groups, lag rings of 8 with a partial last
 ])
 def test_full_form_matches_oracle(scivr, oracle_mod, F, n, ns, K, emax):
     O = oracle_mod
