@@ -273,7 +273,7 @@ def refs_form(scivr, torch, inputs, n=65536, n_refs=8, reps=2, cpu_sample=64, se
     qe = rng.uniform(-0.8, 0.8, (n_refs - 1, prob.F)) / sg
     stream = torch.cuda.current_stream()
     res = {}
-    for key, k in (("chi_only", 1), ("all_states", n_refs)):
+    for key, k, fft in (("chi_only", 1, False), ("all_states", n_refs, False), ("all_states_fft", n_refs, True)):
         ctx = scivr.Context(prob, max_traj=n)
         if k > 1:
             ctx.set_references(pe, qe)
@@ -281,7 +281,10 @@ def refs_form(scivr, torch, inputs, n=65536, n_refs=8, reps=2, cpu_sample=64, se
         def one(i):
             ctx.sample_husimi(seed=seed + i, n_traj=n, stream=stream)
             ctx.propagate(0, prob.n_steps, stream=stream)
-            ctx.accumulate(stream=stream)
+            if fft:
+                ctx.accumulate_fft(stream=stream)
+            else:
+                ctx.accumulate(stream=stream)
 
         one(0)
         torch.cuda.synchronize()
@@ -296,7 +299,8 @@ def refs_form(scivr, torch, inputs, n=65536, n_refs=8, reps=2, cpu_sample=64, se
         ctx.close()
         res[key] = {"wall_s": wall, "traj_ms": kt["trajectory"][1] / max(kt["trajectory"][0], 1),
                     "fourier_ms": kt["fourier"][1] / max(kt["fourier"][0], 1)}
-        print(f"[bench] several reference states: {k} state(s), {wall:.3f} s per pass", file=sys.stderr, flush=True)
+        print(f"[bench] several reference states: {k} state(s){' (FFT form)' if fft else ''}, {wall:.3f} s per pass",
+              file=sys.stderr, flush=True)
     a = res["all_states"]
     steps = n * prob.n_steps
     fl_traj = steps * (traj_flops_per_step(prob.F) + (n_refs - 1) * (12 * prob.F + 10))
@@ -314,6 +318,7 @@ def refs_form(scivr, torch, inputs, n=65536, n_refs=8, reps=2, cpu_sample=64, se
                     f"trajectories, {prob.n_steps} steps, {prob.n_energies} energies",
         "value": steps / a["wall_s"], "unit": "trajectory-steps/s (every state's spectrum)",
         "chi_only_value": steps / res["chi_only"]["wall_s"],
+        "value_with_fft": steps / res["all_states_fft"]["wall_s"],
         "passes": res,
         "roofline": {"kernel": "traj_kernel (multi-reference variant)", "bound": "alu", "achieved": achieved,
                      "peak": FP64_VALU_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": achieved / FP64_VALU_PEAK_TFLOPS,

@@ -180,8 +180,10 @@ scivr_status scivr_accumulate_spectrum(scivr_ctx *ctx, void *stream);
  * autocorrelation summed over the batch is then evaluated on the energy grid.
  * The spectrum agrees with scivr_accumulate_spectrum's to rounding.  No
  * per-trajectory contributions are produced: scivr_read_contributions and
- * the flow's training on this batch then return SCIVR_ESTATE.  At most 4096
- * steps (L <= 8192), else SCIVR_EUNSUPPORTED.  The first call allocates about
+ * the flow's training on this batch then return SCIVR_ESTATE.  With several
+ * reference states (scivr_set_references) each state's spectrum is added, one
+ * transform pass per state.  At most 4096 steps (L <= 8192), else
+ * SCIVR_EUNSUPPORTED.  The first call allocates about
  * 17 MB of scratch on the context's device (SCIVR_ENOMEM if that fails).
  * Other errors as scivr_accumulate_spectrum.
  */
@@ -257,8 +259,8 @@ scivr_status scivr_read_spectrum(scivr_ctx *ctx, double *I_host, int64_t *n_good
  * with a right-hand side per reference state (the phase matrix is shared).
  * Resets the running totals and discards the current batch.  0 <= n_extra
  * <= 7 (SCIVR_EINVAL otherwise); FP64 form only (SCIVR_EUNSUPPORTED for the
- * mixed form; the FFT and double-time accumulations also take one reference
- * state); SCIVR_ESTATE while a propagated batch awaits accumulation;
+ * mixed form; the double-time accumulation also takes one reference state);
+ * SCIVR_ESTATE while a propagated batch awaits accumulation;
  * SCIVR_ENOMEM if the amplitude buffer for the n_extra + 1 states cannot be
  * allocated (the context is then unchanged).  Per-trajectory contributions
  * (scivr_read_contributions) and amplitudes (scivr_read_amplitudes) are

@@ -153,8 +153,6 @@ hipError_t static_scratch_address(int device, void **out)
 
 scivr_status fft_accumulate_check(scivr_ctx *ctx)
 {
-    if (ctx->n_refs > 1)
-        return ctx_fail(ctx, SCIVR_EUNSUPPORTED, "the FFT accumulation takes one reference state (%d set)", ctx->n_refs);
     if (!ctx->have_initial || ctx->steps_done != ctx->n_steps)
         return ctx_fail(ctx, SCIVR_ESTATE, "accumulate needs a fully propagated batch (%d of %d steps)", ctx->steps_done,
                         ctx->n_steps);
@@ -174,23 +172,33 @@ scivr_status fft_accumulate(scivr_ctx *ctx, hipStream_t s, const FftScratch &b, 
                                 ctx->d_scal + SC_ESCALE * ctx->npad, ctx->d_logrho, ctx->d_p0, ctx->d_q0,
                                 ctx->husimi_batch, ctx->n_traj, ctx->npad, ctx->d_weight, ctx->d_goodw_row,
                                 ctx->d_ngood, ctx->d_goodw, s));
+    for (int m = 1; m < ctx->n_refs; ++m)
+        HIPCALL(ctx, launch_ref_good_weights(ctx->d_prob, ctx->F, m, ctx->d_scal + SC_GOOD * ctx->npad, ctx->d_logrho,
+                                             ctx->d_p0, ctx->d_q0, ctx->n_traj, ctx->npad, ctx->d_goodw_row,
+                                             ctx->d_goodw + m, s));
     FftArgs a;
-    a.amp = ctx->d_amp;
     a.amp16 = ctx->d_amp16;
     a.plane = (int64_t)ctx->nt16 * ctx->npad;
     a.weight = ctx->d_weight;
     a.part = b.part;
     a.part_corr = b.pcorr;
     a.n = ctx->n_traj;
-    a.npad = ctx->npad;
+    // FP64 amplitudes are [t][reference state][trajectory]: a time row of one
+    // state is n_refs row blocks apart (several states run in FP64 only)
+    a.npad = (int64_t)ctx->n_refs * ctx->npad;
     a.nt = ctx->nt;
     a.nwg = FFT_NWG;
     a.fold = (L == 2 * (ctx->nt - 1)) ? 1 : 0;
     {
         Timed tm(timed ? ctx : nullptr, s, 2);
-        HIPCALL(ctx, launch_fourier_fft(a, ctx->precision == SCIVR_PRECISION_MIXED, ctx->e_min,
-                                        (ctx->e_max - ctx->e_min) / (double)(ctx->n_energies - 1), ctx->dt,
-                                        ctx->n_energies, b.S, b.corr, b.C, ctx->d_total, s));
+        // one pass per reference state through the same scratch, in stream order
+        for (int m = 0; m < ctx->n_refs; ++m) {
+            a.amp = ctx->d_amp + (int64_t)m * ctx->npad;
+            HIPCALL(ctx, launch_fourier_fft(a, ctx->precision == SCIVR_PRECISION_MIXED, ctx->e_min,
+                                            (ctx->e_max - ctx->e_min) / (double)(ctx->n_energies - 1), ctx->dt,
+                                            ctx->n_energies, b.S, b.corr, b.C,
+                                            ctx->d_total + (int64_t)m * ctx->n_energies, s));
+        }
         tm.done();
     }
     ctx->n_total += ctx->n_traj;

@@ -123,8 +123,6 @@ def test_reference_state_errors(scivr):
     ctx.propagate()
     with pytest.raises(scivr.ScivrError, match="ESTATE"):
         ctx.set_references(np.zeros((1, 2)), np.zeros((1, 2)))  # batch in flight
-    with pytest.raises(scivr.ScivrError, match="EUNSUPPORTED"):
-        ctx.accumulate_fft()
     ctx.accumulate()
     with pytest.raises(scivr.ScivrError, match="EINVAL"):
         ctx.read_spectrum(2)
@@ -161,3 +159,32 @@ def test_reference_spectra_chunked_propagation_identical(scivr, F):
         ctx.close()
     for m in range(4):
         assert np.array_equal(out[0][m], out[1][m]), m
+
+
+@pytest.mark.parametrize("F", [3, 9, 17])
+def test_reference_spectra_by_fft_match_the_gemm(scivr, F):
+    """The FFT-autocorrelation form takes every reference state's amplitudes
+    (one transform pass per state): each state's spectrum and good count equal
+    the GEMM's on the same batch to rounding."""
+    _say(f"[refs] FFT form F={F}")
+    prob = inputs.morse_quartic(F, F, n_steps=200, n_energies=128, e_max=0.1 if F <= 9 else 0.2)
+    pe, qe = _refs(prob, 3, 11 + F)
+    out = {}
+    for form in ("gemm", "fft"):
+        ctx = scivr.Context(prob, max_traj=96)
+        ctx.set_references(pe, qe)
+        ctx.sample_husimi(9, 96)
+        ctx.propagate()
+        if form == "fft":
+            ctx.accumulate_fft()
+        else:
+            ctx.accumulate()
+        out[form] = [ctx.read_spectrum(m) for m in range(4)]
+        ctx.close()
+    for m in range(4):
+        Ig, ngg, ntg = out["gemm"][m]
+        If, ngf, ntf = out["fft"][m]
+        assert ngg == ngf and ntg == ntf, m
+        err = np.max(np.abs(If - Ig)) / np.max(np.abs(Ig))
+        _say(f"[refs] FFT form, ref {m}: max rel diff {err:.2e}")
+        assert err < 1e-12, (m, err)
