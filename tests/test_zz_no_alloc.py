@@ -61,6 +61,35 @@ def test_noalloc_fft_matches_allocating_form_twice(scivr, precision):
         assert np.array_equal(Ia, Ib), np.max(np.abs(Ia - Ib)) / np.max(Ia)
 
 
+def test_noalloc_fft_with_reference_states(scivr):
+    """Several reference states pass through the static scratch one after
+    another: every state's spectrum equals the allocating form's bit for bit."""
+    F, n, ns, K = 6, 300, 400, 128
+    _say(f"[noalloc] three reference states F={F} n={n} steps={ns}")
+    prob = inputs.morse_quartic(F, F, n_steps=ns, n_energies=K, e_max=0.1)
+    rng = np.random.default_rng(23)
+    sg = np.sqrt(prob.gamma)
+    pe = rng.uniform(-0.8, 0.8, (2, F)) * sg
+    qe = rng.uniform(-0.8, 0.8, (2, F)) / sg
+    ctx = scivr.Context(prob, max_traj=n)
+    ctx.set_references(pe, qe)
+    out = []
+    for noalloc in (False, True):
+        ctx.reset_spectrum()
+        ctx.sample_husimi(31, n)
+        ctx.propagate(0, prob.n_steps)
+        if noalloc:
+            ctx.accumulate_fft_noalloc()
+        else:
+            ctx.accumulate_fft()
+        out.append([ctx.read_spectrum(m) for m in range(3)])
+    ctx.close()
+    for m in range(3):
+        (Ia, nga, _), (Ib, ngb, _) = out[0][m], out[1][m]
+        assert nga == ngb and np.max(Ia) > 0
+        assert np.array_equal(Ia, Ib), (m, np.max(np.abs(Ia - Ib)) / np.max(Ia))
+
+
 def test_noalloc_fft_rejects_sequences_beyond_its_scratch(scivr):
     _say("[noalloc] 4097 steps")
     prob = inputs.morse_quartic(2, 2, n_steps=4097, n_energies=64)
