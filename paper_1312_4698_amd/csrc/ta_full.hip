@@ -164,12 +164,12 @@ __device__ inline void rescale(double &dr, double &di)
 }
 
 // Waves per SIMD the register allocator must allow (unified 512-register
-// file).  For 7 <= F <= 12 the kernel needs more than 256 registers and would
+// file).  For 7 <= F <= 16 the kernel would take more than 256 registers and
 // run one wave per SIMD, where nothing hides the LDS round trips of the
 // eliminations; two waves with some spilling are faster.  Smaller F already
 // fits two or more waves.
 template <int F>
-constexpr int full_waves() { return (F >= 7 && F <= 12) ? 2 : 1; }
+constexpr int full_waves() { return (F >= 7 && F <= 16) ? 2 : 1; }
 
 template <int F>
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(full_waves<F>(), 8)))
