@@ -28,9 +28,13 @@
 //    group also carries a cursor on the trajectory itself (positions only,
 //    the same step code), advanced to its next c1 between rounds.  A segment
 //    propagates its tangent map from the identity, takes det A by complex
-//    elimination every step and keeps the branch as the main kernel does;
-//    the groups' terms of each lag are summed in group order and added to the
-//    wave's row part[s][tau][j] (each row belongs to one wave: no atomics).
+//    elimination every step and keeps the branch as the main kernel does.
+//    Each lag leaves det A, the action and the modes' q and p in the group's
+//    ring; every eight lags (every F at F < 8) lanes 0..7 of the group finish
+//    one lag each (|C|, the branch with its increments added in lag order, the
+//    overlap, exp and sincos), and lanes 0..7 of the wave sum the groups'
+//    terms of those lags in group order into the wave's rows part[s][tau][j]
+//    (each row belongs to one wave: no atomics).
 //    Segments do not run the stability monitor: only the trajectory's own
 //    flag (from the propagation) enters the estimate.
 //  * ta_lags_kernel: C(tau) = sum_j weight_j sum_s part[s][tau][j], in fixed
