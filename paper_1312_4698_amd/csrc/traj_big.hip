@@ -44,14 +44,42 @@ template <int F>
 struct alignas(16) BigLds {
     static constexpr int N2 = 2 * F;
     static constexpr int RS = N2 + 1;  // odd row stride of the copy of M
+    static constexpr bool SM_MFMA = N2 < 64;  // a spare product column for sum_k Lambda_ik q_k^2
+    static constexpr int RB = 8;              // time samples per amplitude ring
     union {
         double T[N2 * RS];  // M, row r at T + r RS (after the step)
         double U[32];       // the kicks' mode terms sum_k Lambda_ik q_k^2, row i at U + i
     };
-    double lam[F * F];  // coupling matrix, row-major, zero diagonal
+    // coupling matrix, row-major, zero diagonal (read only where the product
+    // has no spare column for the mode terms)
+    double lam[SM_MFMA ? 1 : F * F];
+    // amplitude ring: per time sample, the raw det(A), the action, the
+    // monitor's flag and every reference state's overlap exponent and phase;
+    // ra holds the branch increments while a ring is finished
+    double rdr[RB], rdi[RB], rS[RB], ra[RB];
+    double rex[RB][MAX_REFS], rph[RB][MAX_REFS];
+    int rgood[RB];
 };
 
 typedef double d4 __attribute__((ext_vector_type(4)));
+
+// lane 0's value in every lane (both 32-bit halves through scalar registers)
+__device__ __attribute__((always_inline)) inline double from_lane0(double v)
+{
+    const unsigned long long u = __double_as_longlong(v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)u);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)(u >> 32));
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// det(A) rescaled by a power of two (the branch only needs its argument)
+__device__ __attribute__((always_inline)) inline void rescale_det(double &dr, double &di)
+{
+    int ex;
+    (void)frexp(fmax(fabs(dr), fabs(di)), &ex);
+    dr = ldexp(dr, -ex);
+    di = ldexp(di, -ex);
+}
 
 // Largest 32-bit key over the wave (every lane gets it).  DPP row shifts
 // 1, 2, 4, 8 leave each row's maximum in its lane 15, row broadcasts 15 and 31
@@ -280,14 +308,16 @@ traj_big_kernel(TrajArgs A, const ProblemDev *__restrict__ P0)
     constexpr int N2 = 2 * F;
     constexpr int RS = BigLds<F>::RS;
     constexpr int FP = F + (F & 1);
-    constexpr bool SM_MFMA = N2 < 64;  // a spare product column for sum_k Lambda_ik q_k^2
+    constexpr bool SM_MFMA = BigLds<F>::SM_MFMA;
+    constexpr int RB = BigLds<F>::RB;
     __shared__ BigLds<F> L;
     __shared__ R qv[FP], pm[FP];
     __shared__ double2 qh[F];  // (4 q_i, h_i) of the kick's Hessian diagonal terms
 
     const int lane = threadIdx.x;
     const ProblemDev *__restrict__ P = P0;
-    for (int idx = lane; idx < F * F; idx += 64) L.lam[idx] = P->lam[(idx / F) * FMAX + idx % F];
+    if constexpr (!SM_MFMA)
+        for (int idx = lane; idx < F * F; idx += 64) L.lam[idx] = P->lam[(idx / F) * FMAX + idx % F];
     const int64_t jr = blockIdx.x;  // one trajectory per workgroup, grid = batch size
     const int64_t NP = A.npad;
     const bool colLane = lane < N2;
@@ -422,6 +452,80 @@ traj_big_kernel(TrajArgs A, const ProblemDev *__restrict__ P0)
         }
     };
 
+    // Finish the ring's nk time samples t0 .. t0 + nk - 1, lane k < nk taking
+    // sample t0 + k: the argument of det(A_t) conj(det(A_{t-dt})) e^{i dt sum
+    // gamma} (on det(A) rescaled by a power of two) advances the continuous
+    // branch, the increments added in time order as one lane per step would;
+    // a non-finite phase or action makes its sample and every later one bad;
+    // then the amplitudes of every reference state.
+    int nk = 0;
+    auto finish_ring = [&](ConstProblem PP, int t0) {
+        lds_order();
+        const bool fin = lane < nk;
+        const int k = fin ? lane : 0;
+        if (fin) {
+            double dr = L.rdr[k], di = L.rdi[k];
+            rescale_det(dr, di);
+            double qr = prev_r, qi = prev_i;
+            if (k > 0) {
+                qr = L.rdr[k - 1];
+                qi = L.rdi[k - 1];
+                rescale_det(qr, qi);
+            }
+            const double ur = dr * qr + di * qi;
+            const double ui = di * qr - dr * qi;
+            const double zr = ur * PP->cos_gdt - ui * PP->sin_gdt;
+            const double zi = ur * PP->sin_gdt + ui * PP->cos_gdt;
+            L.ra[k] = datan2(zi, zr, &PP->mc);
+        }
+        lds_order();
+        double th = theta, phk = 0.0, Sk = 0.0;
+        bool bad = false;
+        if (fin) {
+            for (int kk = 0; kk <= k; ++kk) th += L.ra[kk];
+            phk = 0.5 * (th - PP->sum_gamma * ((double)(t0 + k) * PP->dt));
+            Sk = L.rS[k];
+            bad = !isfinite(phk) || !isfinite(Sk);
+        }
+        const unsigned long long badm = __ballot(fin && bad);
+        if (fin) {
+            const bool g = L.rgood[k] != 0 && (badm & ((2ull << k) - 1ull)) == 0;
+            const int t = t0 + k;
+            if constexpr (!MIXED) {
+                for (int m = 0; m < A.n_refs; ++m) {
+                    double sn, co;
+                    dsincos(L.rph[k][m] + Sk + phk, &PP->mc, &sn, &co);
+                    const double mag = dexp(L.rex[k][m], &PP->mc);
+                    double2 r;
+                    r.x = g ? mag * co : 0.0;
+                    r.y = g ? mag * sn : 0.0;
+                    A.amp[((int64_t)t * A.n_refs + m) * NP + jr] = r;
+                }
+            } else {
+                double sn, co;
+                dsincos(L.rph[k][0] + Sk + phk, &PP->mc, &sn, &co);
+                const double mag = ldexp(dexp(L.rex[k][0], &PP->mc), escale);
+                const float re = g ? (float)(mag * co) : 0.f, im = g ? (float)(mag * sn) : 0.f;
+                _Float16 h[4];
+                split_f16(re, h[0], h[1]);
+                split_f16(im, h[2], h[3]);
+                const int64_t e = ((int64_t)(t >> 3) * NP + jr) * 8 + (t & 7);
+#pragma unroll
+                for (int pl = 0; pl < 4; ++pl) A.amp16[pl * A.plane + e] = h[pl];
+            }
+            for (int kk = k + 1; kk < nk; ++kk) th += L.ra[kk];
+        }
+        // the branch through the ring's last sample, in every lane
+        theta = from_lane0(th);
+        prev_r = L.rdr[nk - 1];
+        prev_i = L.rdi[nk - 1];
+        rescale_det(prev_r, prev_i);
+        phi = 0.5 * (theta - PP->sum_gamma * ((double)(t0 + nk - 1) * PP->dt));
+        if (badm != 0) good = false;
+        lds_order();
+        nk = 0;
+    };
+
     if (A.step_begin == 0) {
         double ph0;
         const double ex0 = overlap(P, 0, ph0);
@@ -435,6 +539,7 @@ traj_big_kernel(TrajArgs A, const ProblemDev *__restrict__ P0)
         // (its amplitudes stay zero; lane 0's flag also covers a non-finite
         // phase or action)
         if (A.stop_flagged && !__builtin_amdgcn_readfirstlane((int)good)) {
+            if (nk > 0) finish_ring(Ps, step - nk + 1);
             if (lane == 0) store_zero(step + 1);
             continue;
         }
@@ -547,7 +652,6 @@ traj_big_kernel(TrajArgs A, const ProblemDev *__restrict__ P0)
         }
 
         const int stp = step + 1;
-        const double t = (double)stp * Ps->dt;
 
         // ---- M to LDS, column `lane` ----
         if (colLane) {
@@ -606,26 +710,34 @@ traj_big_kernel(TrajArgs A, const ProblemDev *__restrict__ P0)
             }
         }
 
-        // continuous branch of the prefactor phase, as in the small-F kernel
-        double ph0;
-        const double ex0 = overlap(Ps, 0, ph0);
-        if (lane == 0) {
-            int ex;
-            (void)frexp(fmax(fabs(dAr), fabs(dAi)), &ex);
-            dAr = ldexp(dAr, -ex);
-            dAi = ldexp(dAi, -ex);
-            const double ur = dAr * prev_r + dAi * prev_i;
-            const double ui = dAi * prev_r - dAr * prev_i;
-            const double zr = ur * Ps->cos_gdt - ui * Ps->sin_gdt;
-            const double zi = ur * Ps->sin_gdt + ui * Ps->cos_gdt;
-            theta += datan2(zi, zr, &Ps->mc);
-            prev_r = dAr;
-            prev_i = dAi;
-            phi = 0.5 * (theta - Ps->sum_gamma * t);
-            if (!isfinite(phi) || !isfinite(S.value())) good = false;
+        // this time sample into the ring (the branch and the amplitudes are
+        // finished eight samples at a time, on samples 8a .. 8a + 7)
+        {
+            double ph0;
+            const double ex0 = overlap(Ps, 0, ph0);
+            if (lane == 0) {
+                L.rdr[nk] = dAr;
+                L.rdi[nk] = dAi;
+                L.rS[nk] = S.value();
+                L.rgood[nk] = good ? 1 : 0;
+                L.rex[nk][0] = ex0;
+                L.rph[nk][0] = ph0;
+            }
+            if constexpr (!MIXED) {
+                for (int m = 1; m < A.n_refs; ++m) {
+                    double ph;
+                    const double ex = overlap(Ps, m, ph);
+                    if (lane == 0) {
+                        L.rex[nk][m] = ex;
+                        L.rph[nk][m] = ph;
+                    }
+                }
+            }
+            ++nk;
+            if ((stp & (RB - 1)) == RB - 1) finish_ring(Ps, stp - nk + 1);
         }
-        store_amplitude(Ps, stp, ex0, ph0);
     }
+    if (nk > 0) finish_ring(opaque(P0), A.step_end - nk + 1);
 
     // ---- save the state ----
     if (modeLane) {
