@@ -220,8 +220,10 @@ scivr_status scivr_accumulate_spectrum_fft_noalloc(scivr_ctx *ctx, void *stream)
  * which equals scivr_accumulate_spectrum's addition when the prefactor is
  * replaced by exp(i (phi(t2) - phi(t1))).  The trajectories' own stability
  * flags (from the propagation) select the good ones; segments are not
- * monitored.  Cost: about n_steps^2 / 2 segment steps per trajectory.  FP64
- * form and F <= 16 only (else SCIVR_EUNSUPPORTED).  The first call allocates
+ * monitored.  Cost: about n_steps^2 / 2 segment steps per trajectory, and
+ * with several reference states (scivr_set_references) one such pass per
+ * state, each adding its own spectrum (scivr_read_lags then returns chi's lag
+ * sums).  FP64 form and F <= 16 only (else SCIVR_EUNSUPPORTED).  The first call allocates
  * a lag buffer of about 16 * n_t * max(max_traj, 4096) bytes (SCIVR_ENOMEM if
  * that fails).  Other errors as scivr_accumulate_spectrum.
  */
@@ -259,8 +261,7 @@ scivr_status scivr_read_spectrum(scivr_ctx *ctx, double *I_host, int64_t *n_good
  * with a right-hand side per reference state (the phase matrix is shared).
  * Resets the running totals and discards the current batch.  0 <= n_extra
  * <= 7 (SCIVR_EINVAL otherwise); FP64 form only (SCIVR_EUNSUPPORTED for the
- * mixed form; the double-time accumulation also takes one reference state);
- * SCIVR_ESTATE while a propagated batch awaits accumulation;
+ * mixed form); SCIVR_ESTATE while a propagated batch awaits accumulation;
  * SCIVR_ENOMEM if the amplitude buffer for the n_extra + 1 states cannot be
  * allocated (the context is then unchanged).  Per-trajectory contributions
  * (scivr_read_contributions) and amplitudes (scivr_read_amplitudes) are

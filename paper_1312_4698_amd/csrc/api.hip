@@ -598,8 +598,6 @@ scivr_status scivr_accumulate_spectrum_full(scivr_ctx *ctx, void *stream)
     if (ctx->precision != SCIVR_PRECISION_FP64)
         return ctx_fail(ctx, SCIVR_EUNSUPPORTED, "the double-time form runs in the FP64 form only");
     if (ctx->F > 16) return ctx_fail(ctx, SCIVR_EUNSUPPORTED, "the double-time form takes F <= 16 (F = %d)", ctx->F);
-    if (ctx->n_refs > 1)
-        return ctx_fail(ctx, SCIVR_EUNSUPPORTED, "the double-time form takes one reference state (%d set)", ctx->n_refs);
     // splits of each trajectory's segment rounds: enough waves to fill the
     // device, at most one split per round
     const int W = 64 / ctx->F;
@@ -626,6 +624,11 @@ scivr_status scivr_accumulate_spectrum_full(scivr_ctx *ctx, void *stream)
                                 ctx->d_scal + SC_ESCALE * ctx->npad, ctx->d_logrho, ctx->d_p0, ctx->d_q0,
                                 ctx->husimi_batch, ctx->n_traj, ctx->npad, ctx->d_weight, ctx->d_goodw_row,
                                 ctx->d_ngood, ctx->d_goodw, s));
+    // the good count of every further reference state (its Husimi mass of the batch)
+    for (int m = 1; m < ctx->n_refs; ++m)
+        HIPCALL(ctx, launch_ref_good_weights(ctx->d_prob, ctx->F, m, ctx->d_scal + SC_GOOD * ctx->npad, ctx->d_logrho,
+                                             ctx->d_p0, ctx->d_q0, ctx->n_traj, ctx->npad, ctx->d_goodw_row,
+                                             ctx->d_goodw + m, s));
     FullArgs a;
     a.prob = ctx->d_prob;
     a.p0 = ctx->d_p0;
@@ -636,14 +639,19 @@ scivr_status scivr_accumulate_spectrum_full(scivr_ctx *ctx, void *stream)
     a.nt = ctx->nt;
     a.n_steps = ctx->n_steps;
     a.splits = ctx->full_splits;
-    HIPCALL(ctx, hipMemsetAsync(a.part, 0, sizeof(double2) * (size_t)a.splits * a.nt * a.npad, s));
     {
         Timed tm(ctx, s, 2);
-        HIPCALL(ctx, launch_ta_full(ctx->F, a, s));
-        HIPCALL(ctx, launch_ta_lags(a, ctx->d_weight, ctx->d_full_C, s));
-        HIPCALL(ctx, launch_fft_spectrum(ctx->d_full_C, ctx->nt, ctx->n_energies, ctx->e_min,
-                                         (ctx->e_max - ctx->e_min) / (double)(ctx->n_energies - 1), ctx->dt,
-                                         ctx->d_total, s));
+        // one pass per reference state through the same lag buffer, in stream
+        // order; reference 0 last, so that scivr_read_lags returns chi's sums
+        for (int m = ctx->n_refs - 1; m >= 0; --m) {
+            a.ref = m;
+            HIPCALL(ctx, hipMemsetAsync(a.part, 0, sizeof(double2) * (size_t)a.splits * a.nt * a.npad, s));
+            HIPCALL(ctx, launch_ta_full(ctx->F, a, s));
+            HIPCALL(ctx, launch_ta_lags(a, ctx->d_weight, ctx->d_full_C, s));
+            HIPCALL(ctx, launch_fft_spectrum(ctx->d_full_C, ctx->nt, ctx->n_energies, ctx->e_min,
+                                             (ctx->e_max - ctx->e_min) / (double)(ctx->n_energies - 1), ctx->dt,
+                                             ctx->d_total + (int64_t)m * ctx->n_energies, s));
+        }
         tm.done();
     }
     ctx->n_total += ctx->n_traj;

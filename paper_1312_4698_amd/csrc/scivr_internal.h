@@ -98,6 +98,7 @@ struct FullArgs {
     double2 *part;          // [splits][nt][npad] per-split lag sums R_j(tau)
     int64_t n, npad;
     int32_t nt, n_steps, splits;
+    int32_t ref;            // reference state whose overlaps form the lag sums (0 = chi)
 };
 hipError_t launch_ta_full(int F, const FullArgs &a, hipStream_t s);
 hipError_t launch_ta_lags(const FullArgs &a, const double *weight, double2 *C, hipStream_t s);

@@ -142,18 +142,19 @@ __device__ inline void full_step(const ProblemDev *P0, FullGroupLds<F> &L, const
     }
 }
 
-// exponent and phase of <chi|p,q> for the modes' positions q[i] and momenta p[i]
+// exponent and phase of <chi_m|p,q> (reference state m, 0 = chi) for the
+// modes' positions q[i] and momenta p[i]
 template <int F>
-__device__ inline double overlap_of(ConstProblem P, const double *q, const double *p, double &ph)
+__device__ inline double overlap_of(ConstProblem P, int m, const double *q, const double *p, double &ph)
 {
     double ex = 0.0;
     ph = 0.0;
 #pragma unroll
     for (int i = 0; i < F; ++i) {
-        const double dqe = P->q_eq[i] - q[i];
-        const double dpe = P->p_eq[i] - p[i];
+        const double dqe = P->ref_q[m][i] - q[i];
+        const double dpe = P->ref_p[m][i] - p[i];
         ex += -0.25 * P->gamma[i] * dqe * dqe - dpe * dpe * P->inv4gamma[i];
-        ph += 0.5 * dqe * (P->p_eq[i] + p[i]);
+        ph += 0.5 * dqe * (P->ref_p[m][i] + p[i]);
     }
     return ex;
 }
@@ -228,7 +229,7 @@ ta_full_kernel(FullArgs A, const ProblemDev *__restrict__ P0)
         L.qv[c] = qc;
         lds_order();
         double ph1;
-        const double ex1 = overlap_of<F>(P, L.qv, L.pm, ph1);  // <chi|z(c1)>
+        const double ex1 = overlap_of<F>(P, A.ref, L.qv, L.pm, ph1);  // <chi_m|z(c1)>
         // the branch through the lags finished so far: theta, and det(A) of the
         // last of them rescaled (kept by the lanes c < RB that finish lags)
         double theta = 0.0, prev_r = 1.0, prev_i = 0.0;
@@ -308,7 +309,7 @@ ta_full_kernel(FullArgs A, const ProblemDev *__restrict__ P0)
                 for (int kk = 0; kk <= c; ++kk) th += L.ra[kk];
                 const double phi = 0.5 * (th - Ps->sum_gamma * ((double)tk * Ps->dt));
                 double ph;
-                const double ex = overlap_of<F>(Ps, L.rq[c], L.rp[c], ph);
+                const double ex = overlap_of<F>(Ps, A.ref, L.rq[c], L.rp[c], ph);
                 const double mag = mod * dexp(ex + ex1, &Ps->mc);
                 double sn, cs;
                 dsincos(phi + ph + L.rS[c] - ph1, &Ps->mc, &sn, &cs);

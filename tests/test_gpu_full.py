@@ -121,6 +121,41 @@ def test_full_form_removes_the_morse_zero_point_shift(scivr, oracle_mod):
     assert sep > 2.5 and abs(full) < 2.0
 
 
+@pytest.mark.parametrize("F,n,ns,K,emax", [(3, 12, 64, 100, 0.06), (9, 4, 30, 64, 0.1)])
+def test_full_form_reference_states_match_oracle(scivr, oracle_mod, F, n, ns, K, emax):
+    """Several reference states with the double-time form (one pass per
+    state): each state's spectrum equals the oracle's double-time form with
+    that state as chi on the same points, its good count being the state's
+    Husimi mass of the batch; the lag sums read back are chi's."""
+    O = oracle_mod
+    _say(f"[full] reference states F={F} n={n} steps={ns}")
+    prob = inputs.morse_quartic(F, F, n_steps=ns, n_energies=K, e_max=emax)
+    rng = np.random.default_rng(70 + F)
+    sg = np.sqrt(prob.gamma)
+    pe = rng.uniform(-0.6, 0.6, (2, F)) * sg
+    qe = rng.uniform(-0.6, 0.6, (2, F)) / sg
+    p0, q0, lr = O.sample_husimi(prob, 60 + F, n)
+    ctx = scivr.Context(prob, max_traj=n)
+    ctx.set_references(pe, qe)
+    ctx.set_initial(p0, q0, lr)
+    ctx.propagate()
+    ctx.accumulate_full()
+    spectra = [ctx.read_spectrum(m) for m in range(3)]
+    R = ctx.read_lags()
+    ctx.close()
+    I0, ng0, R0, _ = _gpu_full(scivr, prob, p0, q0, lr)
+    assert np.array_equal(spectra[0][0], I0) and spectra[0][1] == ng0
+    assert np.array_equal(R, R0)
+    for m in (1, 2):
+        pm = prob.replace(p_eq=pe[m - 1], q_eq=qe[m - 1])
+        ora = O.run_full(pm, p0, q0, lr)
+        I, ng, nt = spectra[m]
+        assert ng == ora.n_good and nt == n
+        err = np.max(np.abs(I - ora.spectrum)) / np.max(np.abs(ora.spectrum))
+        _say(f"[full] reference {m}: max rel diff {err:.2e}")
+        assert err < 1e-9, (m, err)
+
+
 def test_full_form_rejects_what_it_does_not_cover(scivr):
     _say("[full] unsupported forms")
     pm = inputs.morse_quartic(2, 2, n_steps=16, n_energies=16, precision=inputs.PRECISION_MIXED)
